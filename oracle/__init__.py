@@ -1,0 +1,141 @@
+"""Oracle for the GPU solver -- TEST INFRASTRUCTURE ONLY.
+
+Plain CPU implementations of what the GPU path computes, written from the
+paper and from textbook definitions.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the GPU library and its
+Python binding never do, and this package never imports them.
+
+- `pcg`, `spmv`, `residual`, `dot`: FP64 C code in pcg_oracle.c, loaded
+  through ctypes (built with gcc, -O2 -ffp-contract=off).
+- `mlp`: an FP64 numpy multilayer perceptron (forward, backward, Adam).
+- `pod`: proper orthogonal decomposition by the method of snapshots.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pcg_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+CONVERGED, MAXIT, BREAKDOWN = 0, 1, 2
+EINVAL, EDIAG, ENOMEM = -1, -2, -3
+STATUS_NAMES = {0: "CONVERGED", 1: "MAXIT", 2: "BREAKDOWN", -1: "EINVAL", -2: "EDIAG", -3: "ENOMEM"}
+
+
+class OracleInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("status", ctypes.c_int),
+        ("replacements", ctypes.c_int),
+        ("pad", ctypes.c_int),
+        ("relres_recur", ctypes.c_double),
+        ("relres_true", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+def build(out: str = LIB) -> str:
+    """Compile the oracle with gcc: -O2, no fused multiply-add, no fast-math."""
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           SRC, "-o", out + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+_lib = None
+
+
+def lib():
+    """Load the oracle library, building it first if nothing is built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        L.oracle_spmv.argtypes = [ctypes.c_int, P, P, P, P, P]
+        L.oracle_spmv.restype = ctypes.c_int
+        L.oracle_dot.argtypes = [ctypes.c_int, P, P, ctypes.c_int]
+        L.oracle_dot.restype = ctypes.c_double
+        L.oracle_residual.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+        L.oracle_residual.restype = ctypes.c_double
+        L.oracle_pcg.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.POINTER(OracleInfo), P, P]
+        L.oracle_pcg.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr_arrays(a):
+    rowptr = np.ascontiguousarray(a.rowptr, dtype=np.int32)
+    col = np.ascontiguousarray(a.col, dtype=np.int32)
+    val = np.ascontiguousarray(a.val, dtype=np.float64)
+    return rowptr, col, val
+
+
+def spmv(a, x) -> np.ndarray:
+    """y = A x in FP64, rows summed in stored order."""
+    rowptr, col, val = _csr_arrays(a)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty(a.n)
+    rc = lib().oracle_spmv(a.n, _p(rowptr), _p(col), _p(val), _p(x), _p(y))
+    if rc != 0:
+        raise ValueError("oracle_spmv: bad arguments")
+    return y
+
+
+def dot(x, y, mode: int = 0) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return lib().oracle_dot(x.size, _p(x), _p(y), mode)
+
+
+def residual(a, b, x) -> tuple[np.ndarray, float]:
+    """(r = b - A x, ||r||_2)."""
+    rowptr, col, val = _csr_arrays(a)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    r = np.empty(a.n)
+    nr = lib().oracle_residual(a.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), _p(r))
+    return r, nr
+
+
+def relres(a, b, x) -> float:
+    """||b - A x|| / ||b|| in FP64."""
+    _, nr = residual(a, b, x)
+    nb = float(np.sqrt(dot(b, b)))
+    return nr / nb if nb > 0 else nr
+
+
+def pcg(a, b, x0=None, tol: float = 1e-10, maxit: int = 0, precond: str = "jacobi",
+        sum_mode: int = 0, history: bool = False, trace: bool = False):
+    """Run the oracle solve.  Returns (x, info dict[, hist][, trace])."""
+    rowptr, col, val = _csr_arrays(a)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(a.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    mi = a.n if maxit <= 0 else maxit
+    hist = np.full(mi + 1, np.nan) if history else None
+    tr = np.full((mi + 1, 4, a.n), np.nan) if trace else None
+    info = OracleInfo()
+    pc = {"none": 0, "jacobi": 1}[precond]
+    lib().oracle_pcg(a.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), tol, mi, pc, sum_mode,
+                     ctypes.byref(info), _p(hist) if history else None, _p(tr) if trace else None)
+    d = info.as_dict()
+    out = [x, d]
+    if history:
+        out.append(hist[: d["iters"] + 1])
+    if trace:
+        out.append(tr[: d["iters"] + 1])
+    return tuple(out)

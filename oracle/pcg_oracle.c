@@ -1,0 +1,224 @@
+/*
+ * Oracle for the preconditioned conjugate-gradient solve -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded FP64 C.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header or constant with the GPU library and must be built with
+ * -ffp-contract=off so that no multiply-add is fused.
+ *
+ * What it computes (paper, Section IV): the conjugate-gradient method of
+ * Golub and Van Loan for a symmetric positive-definite matrix stored in CSR,
+ * with a continue-condition that ends the loop early, at tolerance 1e-10
+ * (Table I caption), with at most N iterations (the "132651 loop").  The
+ * paper does not print the algorithm; the readings taken here are:
+ *   - tolerance is on the unpreconditioned 2-norm  ||b - A x|| / ||b||;
+ *   - x0 defaults to zero (the caller passes it in x);
+ *   - preconditioner M = diag(A) (Jacobi) or M = I ("none", the paper's
+ *     flop accounting);
+ *   - when the recurrence residual passes the test, the true residual
+ *     b - A x is computed; if it also passes the solve has converged,
+ *     otherwise r is replaced by it and the iteration continues;
+ *   - "iterations" counts products A p inside the loop;
+ *   - breakdown (p'Ap <= 0, r'z <= 0, or a non-finite scalar) ends the
+ *     solve with a status instead of a result: CG needs an SPD system.
+ * Sums run sequentially from index 0 upward (or pairwise, as a second
+ * rounding order for self-consistency checks); a CSR row is summed in
+ * stored column order.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_CONVERGED 0
+#define ORC_MAXIT 1
+#define ORC_BREAKDOWN 2
+#define ORC_EINVAL (-1)
+#define ORC_EDIAG (-2)
+#define ORC_ENOMEM (-3)
+
+typedef struct {
+    int iters;
+    int status;
+    int replacements;
+    int pad;
+    double relres_recur; /* ||r_k|| / ||b|| from the recurrence at exit */
+    double relres_true;  /* ||b - A x|| / ||b|| for the returned x      */
+} oracle_info;
+
+/* y = A x, each row summed in stored column order. */
+int oracle_spmv(int n, const int *rowptr, const int *col, const double *val,
+                const double *x, double *y)
+{
+    if (n < 0 || !rowptr || !col || !val || !x || !y) return ORC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) s += val[k] * x[col[k]];
+        y[i] = s;
+    }
+    return 0;
+}
+
+static double sum_pairwise(const double *a, const double *b, size_t lo, size_t hi)
+{
+    if (hi - lo <= 8) {
+        double s = 0.0;
+        for (size_t i = lo; i < hi; ++i) s += a[i] * b[i];
+        return s;
+    }
+    size_t mid = lo + (hi - lo) / 2;
+    return sum_pairwise(a, b, lo, mid) + sum_pairwise(a, b, mid, hi);
+}
+
+/* a . b ; mode 0 = sequential from index 0, mode 1 = pairwise halving. */
+double oracle_dot(int n, const double *a, const double *b, int mode)
+{
+    if (n <= 0) return 0.0;
+    if (mode == 1) return sum_pairwise(a, b, 0, (size_t)n);
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* r = b - A x ; returns ||r||_2 (sequential sum), or -1 on bad arguments. */
+double oracle_residual(int n, const int *rowptr, const int *col, const double *val,
+                       const double *b, const double *x, double *r)
+{
+    if (oracle_spmv(n, rowptr, col, val, x, r) != 0) return -1.0;
+    for (int i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    return sqrt(oracle_dot(n, r, r, 0));
+}
+
+static void snapshot(double *trace, int n, int k, const double *x, const double *r,
+                     const double *z, const double *p)
+{
+    if (!trace) return;
+    double *t = trace + (size_t)k * 4 * (size_t)n;
+    memcpy(t, x, sizeof(double) * (size_t)n);
+    memcpy(t + n, r, sizeof(double) * (size_t)n);
+    if (z) memcpy(t + 2 * (size_t)n, z, sizeof(double) * (size_t)n);
+    if (p) memcpy(t + 3 * (size_t)n, p, sizeof(double) * (size_t)n);
+}
+
+/*
+ * Solve A x = b.  x holds x0 on entry and the result on exit.
+ *   precond  : 0 = none (M = I), 1 = Jacobi (M = diag A)
+ *   sum_mode : 0 = sequential dot products, 1 = pairwise
+ *   maxit    : <= 0 means n
+ *   hist     : optional, maxit+1 doubles: hist[0] = ||r_0||/||b||, hist[k] =
+ *              recurrence ||r_k||/||b|| after iteration k (before any
+ *              replacement)
+ *   trace    : optional, (maxit+1) * 4n doubles: x_k, r_k, z_k, p_k after
+ *              iteration k (z_k, p_k left untouched when the loop ends at k)
+ */
+int oracle_pcg(int n, const int *rowptr, const int *col, const double *val,
+               const double *b, double *x, double tol, int maxit, int precond,
+               int sum_mode, oracle_info *info, double *hist, double *trace)
+{
+    if (n <= 0 || !rowptr || !col || !val || !b || !x || !info || !(tol >= 0.0))
+        return ORC_EINVAL;
+    if (maxit <= 0) maxit = n;
+    memset(info, 0, sizeof(*info));
+
+    double *diag = malloc(sizeof(double) * (size_t)n);
+    double *r = malloc(sizeof(double) * (size_t)n);
+    double *z = malloc(sizeof(double) * (size_t)n);
+    double *p = malloc(sizeof(double) * (size_t)n);
+    double *q = malloc(sizeof(double) * (size_t)n);
+    if (!diag || !r || !z || !p || !q) {
+        free(diag); free(r); free(z); free(p); free(q);
+        return ORC_ENOMEM;
+    }
+    int status = ORC_MAXIT;
+
+    /* M = diag(A) for Jacobi; every diagonal entry must be present and > 0. */
+    for (int i = 0; i < n; ++i) {
+        diag[i] = 1.0;
+        if (precond == 1) {
+            double d = 0.0;
+            int found = 0;
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                if (col[k] == i) { d += val[k]; found = 1; }
+            if (!found || !(d > 0.0)) { status = ORC_EDIAG; goto out; }
+            diag[i] = d;
+        }
+    }
+
+    double nb = sqrt(oracle_dot(n, b, b, sum_mode));
+    if (nb == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        info->relres_recur = 0.0;
+        info->relres_true = 0.0;
+        if (hist) hist[0] = 0.0;
+        status = ORC_CONVERGED;
+        goto out;
+    }
+    double thr = tol * nb;
+
+    /* r0 = b - A x0 */
+    oracle_spmv(n, rowptr, col, val, x, r);
+    for (int i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    double rn = sqrt(oracle_dot(n, r, r, sum_mode));
+    if (hist) hist[0] = rn / nb;
+    info->relres_recur = rn / nb;
+    if (rn <= thr) {
+        info->relres_true = rn / nb;
+        snapshot(trace, n, 0, x, r, NULL, NULL);
+        status = ORC_CONVERGED;
+        goto out;
+    }
+    /* z0 = M^{-1} r0, p0 = z0, rho0 = r0' z0 */
+    for (int i = 0; i < n; ++i) z[i] = r[i] / diag[i];
+    memcpy(p, z, sizeof(double) * (size_t)n);
+    double rho = oracle_dot(n, r, z, sum_mode);
+    snapshot(trace, n, 0, x, r, z, p);
+
+    int k = 0;
+    while (k < maxit) {
+        oracle_spmv(n, rowptr, col, val, p, q);           /* q = A p       */
+        double sigma = oracle_dot(n, p, q, sum_mode);       /* sigma = p'q   */
+        if (!(sigma > 0.0) || !isfinite(sigma)) { status = ORC_BREAKDOWN; break; }
+        double alpha = rho / sigma;
+        for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+        ++k;
+        rn = sqrt(oracle_dot(n, r, r, sum_mode));
+        if (hist) hist[k] = rn / nb;
+        info->relres_recur = rn / nb;
+        if (rn <= thr) {                                    /* continue-condition */
+            oracle_spmv(n, rowptr, col, val, x, q);
+            for (int i = 0; i < n; ++i) q[i] = b[i] - q[i];
+            double tn = sqrt(oracle_dot(n, q, q, sum_mode));
+            if (tn <= thr) {
+                snapshot(trace, n, k, x, r, NULL, NULL);
+                status = ORC_CONVERGED;
+                break;
+            }
+            memcpy(r, q, sizeof(double) * (size_t)n);       /* residual replacement */
+            info->replacements += 1;
+        }
+        for (int i = 0; i < n; ++i) z[i] = r[i] / diag[i];
+        double rho_new = oracle_dot(n, r, z, sum_mode);
+        if (!(rho_new > 0.0) || !isfinite(rho_new)) {
+            snapshot(trace, n, k, x, r, z, NULL);
+            status = ORC_BREAKDOWN;
+            break;
+        }
+        double beta = rho_new / rho;
+        rho = rho_new;
+        for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        snapshot(trace, n, k, x, r, z, p);
+    }
+    info->iters = k;
+    {
+        /* Reported, not part of the method: the true residual of the returned x. */
+        oracle_spmv(n, rowptr, col, val, x, q);
+        for (int i = 0; i < n; ++i) q[i] = b[i] - q[i];
+        info->relres_true = sqrt(oracle_dot(n, q, q, sum_mode)) / nb;
+    }
+
+out:
+    info->status = status;
+    free(diag); free(r); free(z); free(p); free(q);
+    return status;
+}

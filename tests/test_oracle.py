@@ -1,0 +1,175 @@
+"""Pins for the FP64 conjugate-gradient oracle, against things other than itself.
+
+The method is the conjugate-gradient iteration for SPD systems (Section IV,
+after Golub and Van Loan) with tolerance 1e-10 (Table I caption).  Each pin
+below comes from the mathematics of CG or from a library routine solving the
+same special case:
+  - dense Cholesky solves of the same systems (LAPACK via scipy);
+  - residual orthogonality r_i' M^-1 r_j = 0 and A-conjugacy p_i' A p_j = 0;
+  - monotone decrease of the A-norm error and the Chebyshev bound;
+  - finite termination: k distinct eigenvalues => at most k iterations;
+  - degenerate inputs: b = 0, x0 = x*, maxit = 1, indefinite A, NaN input.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+import workloads as W
+
+
+def dense_csr(a_dense):
+    n = a_dense.shape[0]
+    rowptr, col, val = [0], [], []
+    for i in range(n):
+        nz = np.nonzero(a_dense[i])[0]
+        col.extend(nz.tolist())
+        val.extend(a_dense[i, nz].tolist())
+        rowptr.append(len(col))
+    return W.CSR(n, np.array(rowptr, np.int32), np.array(col, np.int32), np.array(val, np.float64))
+
+
+def test_spmv_brute_force():
+    rng = np.random.default_rng(0)
+    for n in (1, 5, 17):
+        d = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.4)
+        a = dense_csr(d)
+        x = rng.standard_normal(n)
+        y = oracle.spmv(a, x)
+        assert np.max(np.abs(y - d @ x)) <= 1e-14 * max(1.0, np.max(np.abs(d) @ np.abs(x)))
+    a, _ = W.problem(6, 2)
+    x = rng.standard_normal(a.n)
+    y = oracle.spmv(a, x)
+    ref = a.to_dense() @ x
+    bound = 1e-14 * (np.abs(a.to_dense()) @ np.abs(x))
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+@pytest.mark.parametrize("n,seed,pc", [(4, 0, "jacobi"), (6, 1, "jacobi"), (7, 2, "none"), (8, 3, "jacobi")])
+def test_cg_matches_cholesky(n, seed, pc):
+    a, b = W.problem(n, seed)
+    d = a.to_dense()
+    xc = sla.cho_solve(sla.cho_factor(d), b)
+    x, info = oracle.pcg(a, b, tol=1e-10, precond=pc)
+    assert info["status"] == oracle.CONVERGED
+    assert info["relres_true"] <= 1e-10
+    kappa = np.linalg.cond(d)
+    # Perturbation bound ||x - x*|| / ||x*|| <= kappa ||b - A x|| / ||b||, plus Cholesky's own error.
+    err = np.linalg.norm(x - xc) / np.linalg.norm(xc)
+    assert err <= kappa * info["relres_true"] * 1.01 + kappa * 1e-15
+    # And CG really is that close in practice: x agrees with Cholesky far below the bound.
+    assert err <= 1e-6
+
+
+def test_cg_well_conditioned_to_roundoff():
+    rng = np.random.default_rng(4)
+    n = 40
+    g = rng.standard_normal((n, n))
+    d = g @ g.T / n + 3 * np.eye(n)
+    b = rng.standard_normal(n)
+    x, info = oracle.pcg(dense_csr(d), b, tol=1e-14, precond="jacobi")
+    xc = sla.cho_solve(sla.cho_factor(d), b)
+    assert info["status"] == oracle.CONVERGED and info["iters"] <= n
+    assert np.linalg.norm(x - xc) / np.linalg.norm(xc) <= 1e-12
+
+
+@pytest.mark.parametrize("pc", ["jacobi", "none"])
+def test_invariants(pc):
+    # Orthogonality r_i' z_j = 0, conjugacy p_i' A p_j = 0, monotone A-norm error, Chebyshev bound.
+    a, b = W.problem(5, 7)
+    d = a.to_dense()
+    xs = sla.cho_solve(sla.cho_factor(d), b)
+    x, info, tr = oracle.pcg(a, b, tol=1e-10, precond=pc, trace=True)
+    k = info["iters"]
+    assert info["status"] == oracle.CONVERGED and k >= 10
+    X, R, Z, P = tr[:, 0], tr[:, 1], tr[:, 2], tr[:, 3]
+    m = min(k, 12)  # exact orthogonality holds for the first steps before rounding erodes it
+    for i in range(m):
+        for j in range(i):
+            rz = R[i] @ Z[j] / (np.linalg.norm(R[i]) * np.linalg.norm(Z[j]))
+            pap = P[i] @ d @ P[j] / np.sqrt((P[i] @ d @ P[i]) * (P[j] @ d @ P[j]))
+            assert abs(rz) < 1e-8, (i, j, rz)
+            assert abs(pap) < 1e-8, (i, j, pap)
+    # Recurrence residual equals the true residual early on.
+    for i in range(m):
+        assert np.linalg.norm(R[i] - (b - d @ X[i])) <= 1e-12 * np.linalg.norm(b)
+    e = X - xs
+    anorm = np.sqrt(np.einsum("ki,ij,kj->k", e, d, e))
+    assert np.all(np.diff(anorm) <= 1e-12 * anorm[0])
+    # ||e_k||_A <= 2 ((sqrt(kappa)-1)/(sqrt(kappa)+1))^k ||e_0||_A with kappa of M^-1 A.
+    dinv = 1 / np.sqrt(np.diag(d)) if pc == "jacobi" else np.ones(a.n)
+    ev = np.linalg.eigvalsh(dinv[:, None] * d * dinv[None, :])
+    kap = ev[-1] / ev[0]
+    rate = (np.sqrt(kap) - 1) / (np.sqrt(kap) + 1)
+    ks = np.arange(len(anorm))
+    assert np.all(anorm <= 2 * rate ** ks * anorm[0] * (1 + 1e-9) + 1e-14 * anorm[0])
+
+
+def test_distinct_eigenvalues_finite_termination():
+    rng = np.random.default_rng(1)
+    n = 30
+    u = rng.standard_normal(n)
+    d = np.eye(n) + np.outer(u, u)  # eigenvalues {1, 1 + |u|^2}
+    x, info = oracle.pcg(dense_csr(d), rng.standard_normal(n), tol=1e-12, precond="none")
+    assert info["status"] == oracle.CONVERGED and info["iters"] == 2
+    d3 = np.diag(np.repeat([1.0, 4.0, 9.0], 10))
+    x, info = oracle.pcg(dense_csr(d3), rng.standard_normal(n), tol=1e-12, precond="none")
+    assert info["iters"] == 3
+    # A diagonal matrix under Jacobi is the identity after preconditioning: one step.
+    dd = np.diag(rng.uniform(1, 100, n))
+    b = rng.standard_normal(n)
+    x, info = oracle.pcg(dense_csr(dd), b, tol=1e-14, precond="jacobi")
+    assert info["iters"] == 1 and np.allclose(x, b / np.diag(dd), rtol=1e-15)
+
+
+def test_termination_within_n():
+    a, b = W.problem(3, 9)
+    x, info = oracle.pcg(a, b, tol=1e-12)
+    assert info["status"] == oracle.CONVERGED and info["iters"] <= a.n
+
+
+def test_degenerate_cases():
+    a, b = W.problem(5, 3)
+    x, info = oracle.pcg(a, np.zeros(a.n), x0=np.ones(a.n))
+    assert info["status"] == oracle.CONVERGED and info["iters"] == 0 and not x.any()
+    xs = sla.cho_solve(sla.cho_factor(a.to_dense()), b)
+    x, info = oracle.pcg(a, b, x0=xs)
+    assert info["status"] == oracle.CONVERGED and info["iters"] == 0
+    x, info = oracle.pcg(a, b, maxit=1)
+    assert info["status"] == oracle.MAXIT and info["iters"] == 1
+    bn = b.copy()
+    bn[3] = np.nan
+    x, info = oracle.pcg(a, bn)
+    assert info["status"] == oracle.BREAKDOWN
+    # Indefinite: flip one diagonal block sign.
+    ind = dense_csr(np.diag([1.0, 2.0, -3.0, 4.0]))
+    x, info = oracle.pcg(ind, np.ones(4), precond="none")
+    assert info["status"] == oracle.BREAKDOWN
+    # Jacobi needs a positive diagonal.
+    bad = dense_csr(np.array([[0.0, 1.0], [1.0, 2.0]]))
+    x, info = oracle.pcg(bad, np.ones(2), precond="jacobi")
+    assert info["status"] == oracle.EDIAG
+
+
+def test_history_matches_true_residual_at_exit():
+    a, b = W.problem(8, 0)
+    x, info, hist, tr = oracle.pcg(a, b, history=True, trace=True)
+    assert len(hist) == info["iters"] + 1
+    # Early on, the recurrence residual norm equals the true residual norm of the iterate.
+    d, nb = a.to_dense(), np.linalg.norm(b)
+    for k in range(8):
+        assert abs(hist[k] - np.linalg.norm(b - d @ tr[k, 0]) / nb) <= 1e-12 * hist[0]
+    assert hist[-1] <= 1e-10 < hist[-2]
+    assert abs(oracle.relres(a, b, x) - info["relres_true"]) <= 1e-3 * info["relres_true"]
+
+
+def test_self_consistency_pairwise_16():
+    # Two rounding orders of the same method: the GPU parity target (+-2 iterations,
+    # solution rel. error 1e-8) must be attainable between them.
+    a, b = W.problem(16, 0)
+    x0, i0 = oracle.pcg(a, b, sum_mode=0)
+    x1, i1 = oracle.pcg(a, b, sum_mode=1)
+    assert abs(i0["iters"] - i1["iters"]) <= 2
+    assert np.linalg.norm(x0 - x1) / np.linalg.norm(x0) <= 1e-8
+    xm0, xm1 = x0 - x0.mean(), x1 - x1.mean()
+    assert np.linalg.norm(xm0 - xm1) / np.linalg.norm(xm0) <= 1e-6

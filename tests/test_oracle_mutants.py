@@ -1,0 +1,113 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case copies the oracle source, plants one mistake (a wrong sign, a
+dropped term, a transposed operand, a wrong index, an off-by-one), compiles it
+on the CPU, and checks that at least one pin rejects the mutant.  Nothing here
+touches the GPU library.
+"""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+import workloads as W
+
+MUTANTS = {
+    "spmv_wrong_index": ("val[k] * x[col[k]]", "val[k] * x[i]"),
+    "spmv_drops_last_entry": ("k < rowptr[i + 1]; ++k) s +=", "k < rowptr[i + 1] - 1; ++k) s +="),
+    "residual_sign": ("r[i] = r[i] - alpha * q[i]", "r[i] = r[i] + alpha * q[i]"),
+    "x_update_sign": ("x[i] = x[i] + alpha * p[i]", "x[i] = x[i] - alpha * p[i]"),
+    "alpha_inverted": ("alpha = rho / sigma", "alpha = sigma / rho"),
+    "beta_inverted": ("beta = rho_new / rho", "beta = rho / rho_new"),
+    "direction_drops_beta": ("p[i] = z[i] + beta * p[i]", "p[i] = z[i]"),
+    "jacobi_multiplies": ("z[i] = r[i] / diag[i];\n        double rho_new", "z[i] = r[i] * diag[i];\n        double rho_new"),
+    "initial_residual_sign": ("for (int i = 0; i < n; ++i) r[i] = b[i] - r[i];\n    double rn",
+                              "for (int i = 0; i < n; ++i) r[i] = r[i] - b[i];\n    double rn"),
+    "norm_without_sqrt": ("rn = sqrt(oracle_dot(n, r, r, sum_mode));\n        if (hist)",
+                          "rn = (oracle_dot(n, r, r, sum_mode));\n        if (hist)"),
+    "p_dot_wrong_operand": ("sigma = oracle_dot(n, p, q, sum_mode)", "sigma = oracle_dot(n, q, q, sum_mode)"),
+}
+
+
+def _pins_pass() -> bool:
+    """A compact subset of the oracle pins; True when every one holds."""
+    try:
+        rng = np.random.default_rng(0)
+        a, b = W.problem(6, 1)
+        d = a.to_dense()
+        x = rng.standard_normal(a.n)
+        if np.max(np.abs(oracle.spmv(a, x) - d @ x)) > 1e-12:
+            return False
+        xc = sla.cho_solve(sla.cho_factor(d), b)
+        xs, info = oracle.pcg(a, b, tol=1e-10)
+        if info["status"] != oracle.CONVERGED or np.linalg.norm(xs - xc) > 1e-6 * np.linalg.norm(xc):
+            return False
+        if np.linalg.norm(b - d @ xs) > 1e-10 * np.linalg.norm(b) * 1.0001:
+            return False
+        xs, info, hist, tr = oracle.pcg(a, b, tol=1e-10, history=True, trace=True)
+        nb = np.linalg.norm(b)
+        for k in range(6):
+            if abs(hist[k] - np.linalg.norm(b - d @ tr[k, 0]) / nb) > 1e-10 * hist[0]:
+                return False
+        P = tr[:, 3]
+        for i in range(1, 6):
+            pap = P[i] @ d @ P[0] / np.sqrt((P[i] @ d @ P[i]) * (P[0] @ d @ P[0]))
+            if not abs(pap) < 1e-8:
+                return False
+        n = 30
+        u = rng.standard_normal(n)
+        x, info = oracle.pcg(
+            W.CSR(n, np.arange(0, n * n + 1, n, dtype=np.int32), np.tile(np.arange(n, dtype=np.int32), n),
+                  (np.eye(n) + np.outer(u, u)).ravel()),
+            rng.standard_normal(n), tol=1e-12, precond="none")
+        return info["status"] == oracle.CONVERGED and info["iters"] == 2
+    except Exception:
+        return False
+
+
+@pytest.fixture
+def swap_lib():
+    saved = oracle._lib
+    yield
+    oracle._lib = saved
+
+
+def _load_variant(src_text, tmp):
+    import ctypes
+
+    c = os.path.join(tmp, "m.c")
+    so = os.path.join(tmp, "m.so")
+    with open(c, "w") as f:
+        f.write(src_text)
+    subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", c, "-o", so, "-lm"],
+                   check=True)
+    oracle._lib = None
+    saved = oracle.LIB
+    oracle.LIB = so
+    try:
+        oracle.lib()
+    finally:
+        oracle.LIB = saved
+
+
+def test_unmutated_copy_passes(swap_lib):
+    with open(oracle.SRC) as f:
+        src = f.read()
+    with tempfile.TemporaryDirectory() as tmp:
+        _load_variant(src, tmp)
+        assert _pins_pass()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, swap_lib):
+    with open(oracle.SRC) as f:
+        src = f.read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    with tempfile.TemporaryDirectory() as tmp:
+        _load_variant(src.replace(old, new), tmp)
+        assert not _pins_pass(), f"pins did not catch {name}"

@@ -1,0 +1,117 @@
+"""Pins for the synthetic Q1-hex systems (input generation, not the solver).
+
+The paper fixes N = 132651 and NNZ = 3442951 (Section IV and the caption of
+Table I); the rest is fixed by the textbook trilinear element.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+
+
+def _m1(n):
+    # 1-D linear element on [0, 1], written out independently of the generator.
+    h = 1.0 / (n - 1)
+    m = np.diag(np.full(n, 2 * h / 3))
+    m[0, 0] = m[-1, -1] = h / 3
+    m += np.diag(np.full(n - 1, h / 6), 1) + np.diag(np.full(n - 1, h / 6), -1)
+    return m
+
+
+def _k1(n):
+    h = 1.0 / (n - 1)
+    k = np.diag(np.full(n, 2 / h))
+    k[0, 0] = k[-1, -1] = 1 / h
+    k += np.diag(np.full(n - 1, -1 / h), 1) + np.diag(np.full(n - 1, -1 / h), -1)
+    return k
+
+
+def test_paper_size_exact():
+    # Section IV: N=132651, NNZ=3442951 -- reproduced exactly at 51^3.
+    a, _ = W.problem(51, 0)
+    assert a.n == 132651 and a.nnz == 3442951
+    assert W.pattern_size(16) == (4096, 97336)
+    assert W.pattern_size(128) == (2097152, 55742968)
+
+
+@pytest.mark.parametrize("n", [3, 7, 16])
+def test_row_histogram_and_sorted_columns(n):
+    a, _ = W.problem(n, 0)
+    cnt = np.diff(a.rowptr)
+    hist = {int(k): int(v) for k, v in zip(*np.unique(cnt, return_counts=True))}
+    want = {8: 8, 12: 12 * (n - 2), 18: 6 * (n - 2) ** 2, 27: (n - 2) ** 3}
+    assert hist == {k: v for k, v in want.items() if v}
+    for i in range(a.n):
+        c = a.col[a.rowptr[i]:a.rowptr[i + 1]]
+        assert np.all(np.diff(c) > 0) and i in c
+
+
+def test_bitwise_symmetric():
+    a, _ = W.problem(16, 0)
+    s = a.to_scipy()
+    d = (s - s.T).tocoo()
+    assert d.nnz == 0 or np.all(d.data == 0.0)
+
+
+def test_constants_in_kernel_of_stiffness():
+    # K 1 = 0 for any sigma, so A 1 = c M 1 and 1'A1 = c |Omega| = c.
+    n = 12
+    a, _ = W.problem(n, 5)
+    m = W.mass_matrix(n).to_scipy()
+    one = np.ones(a.n)
+    a1 = a.to_scipy() @ one
+    scale = abs(a.to_scipy()) @ one
+    assert np.all(np.abs(a1 - W.MASS_COEF * (m @ one)) <= 1e-13 * scale)
+    assert abs(one @ a1 - W.MASS_COEF) <= 1e-12
+
+
+def test_interior_stencil_constant_sigma():
+    n, s, c = 9, 2.5, 1e-3
+    a = W.assemble(n, np.full((n - 1,) * 3, s), c).to_dense()
+    h = 1.0 / (n - 1)
+    i = 4 + n * 4 + n * n * 4
+    assert a[i, i] == pytest.approx(h * (8 / 3) * s + c * h ** 3 * 8 / 27, rel=1e-14)
+    assert a[i, i + 1] == pytest.approx(c * h ** 3 * 2 / 27, rel=1e-14)
+    assert a[i, i + 1 + n] == pytest.approx(-s * h / 6 + c * h ** 3 / 54, rel=1e-14)
+    assert a[i, i + 1 + n + n * n] == pytest.approx(-s * h / 12 + c * h ** 3 / 216, rel=1e-14)
+    assert a[i].sum() == pytest.approx(c * h ** 3, rel=1e-9)
+
+
+def test_kronecker_form_constant_sigma():
+    # A = s (K1 x M1 x M1 + M1 x K1 x M1 + M1 x M1 x K1) + c M1 x M1 x M1, an independent build.
+    n, s, c = 6, 0.7, 1e-3
+    a = W.assemble(n, np.full((n - 1,) * 3, s), c).to_dense()
+    m, k = _m1(n), _k1(n)
+    kr = lambda x, y, z: np.kron(x, np.kron(y, z))
+    ref = s * (kr(k, m, m) + kr(m, k, m) + kr(m, m, k)) + c * kr(m, m, m)
+    assert np.max(np.abs(a - ref)) <= 1e-15 * np.max(np.abs(ref)) * 10
+
+
+def test_spd_small():
+    a, _ = W.problem(5, 1)
+    ev = np.linalg.eigvalsh(a.to_dense())
+    assert ev[0] > 0
+
+
+def test_seed_order_sigma_then_b():
+    a1, b1 = W.problem(6, 11)
+    rng = np.random.default_rng(11)
+    rng.standard_normal(5 ** 3)
+    assert np.array_equal(b1, rng.uniform(-1, 1, 6 ** 3))
+
+
+def test_source_rhs_equals_mass_times_field():
+    fam = W.source_family(n=9, count=3, k=4, seed=3)
+    m = W.mass_matrix(9).to_scipy()
+    b = fam.rhs([0, 1, 2])
+    for s in range(3):
+        ref = m @ fam.source_field(s)
+        assert np.max(np.abs(b[s] - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert fam.theta().shape == (3, 12)
+
+
+def test_batch_sizes_in_range():
+    sys = W.batch_systems(count=3)
+    for n, a, b in sys:
+        assert 12 <= n <= 48 and a.n == n ** 3 and a.nnz == (3 * n - 2) ** 3 and b.shape == (a.n,)
