@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark: time-to-1e-10 Jacobi-PCG solve and SpMV bandwidth on one MI355X.
+
+Workload: the 51^3 Q1-hex sigma+mass system (N = 132651, nnz = 3442951, the
+paper's matrix size), b ~ U[-1, 1] (seed 0), x0 = 0, tol = 1e-10 on
+||b - A x|| / ||b||.  One step is one full solve.  Prints ONE JSON line on
+stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-10 solve (s) + SpMV HBM GB/s at 51^3; mixed/batched/learned vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def spmv_bytes(n, nnz, vb=8, ib=4):
+    return (vb + ib) * nnz + ib * (n + 1) + 2 * vb * n
+
+
+def iter_bytes(n, nnz, vb=8, ib=4):
+    # step A: matrix + z, p_old read + p_new, q written; step B: p, q, dinv read, x, r read+written, z written
+    return (vb + ib) * nnz + ib * (n + 1) + 12 * vb * n
+
+
+def solve_bytes(n, nnz, iters, checks, vb=8, ib=4):
+    matrix = (vb + ib) * nnz + ib * (n + 1)
+    setup = matrix + 5 * vb * n  # x, b, dinv read; r, z written
+    return setup + iters * iter_bytes(n, nnz, vb, ib) + checks * (matrix + 5 * vb * n)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=51, help="grid edge (51 = the paper's N and NNZ)")
+    ap.add_argument("--spmv-reps", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solver runs the whole system on a single MI355X "
+              "(multi-GPU sharding is a design note, not part of this build).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1107_0538_amd import Solver
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"building {args.n}^3 system")
+    a, b = W.problem(args.n, 0)
+    n, nnz = a.n, a.nnz
+    s = Solver(a, autotune=not args.no_autotune)
+    cfg = s.config()
+    log(f"config {cfg}")
+    stream = torch.cuda.current_stream()
+    bt = torch.as_tensor(b, device=dev)
+
+    # --- SpMV bandwidth (warm: repeated products; cold: 2 GB written between products)
+    xv = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, n), device=dev)
+    yv = torch.empty_like(xv)
+    for _ in range(10):
+        s.spmv(xv, yv)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.spmv_reps):
+        s.spmv(xv, yv)
+    e1.record(stream)
+    e1.synchronize()
+    spmv_us = e0.elapsed_time(e1) * 1e3 / args.spmv_reps
+    flush = torch.empty(2 * 1024 ** 3 // 4, dtype=torch.float32, device=dev)
+    cold = []
+    for r in range(20):
+        flush.fill_(float(r))
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        s.spmv(xv, yv)
+        c1.record(stream)
+        c1.synchronize()
+        cold.append(c0.elapsed_time(c1) * 1e3)
+    del flush
+    sb = spmv_bytes(n, nnz)
+    log(f"spmv {spmv_us:.2f} us warm ({sb / spmv_us / 1e3:.0f} GB/s), cold median {statistics.median(cold):.2f} us")
+
+    # --- time-to-solution
+    x = torch.zeros_like(bt)
+    for _ in range(args.warmup):
+        x.zero_()
+        s.cg_solve(bt, x)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x.zero_()
+        infos.append(s.cg_solve(bt, x))
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    it = infos[-1]
+    assert all(i["status"] == 0 for i in infos), infos[-1]
+    kern_s = statistics.mean(i["seconds"] for i in infos)
+    log(f"solve {wall * 1e3:.3f} ms wall, {kern_s * 1e3:.3f} ms kernel, iters {it['iters']}, "
+        f"relres {it['relres_true']:.3e}")
+    checks = 1 + it["replacements"]
+    sbytes = solve_bytes(n, nnz, it["iters"], checks)
+    achieved = sbytes / kern_s / 1e9
+    flops_iter = 2 * nnz + 10 * n  # the paper's gflops convention (Table I)
+
+    out = {
+        "metric": METRIC,
+        "value": wall,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"jacobi-pcg fp64, q1hex {args.n}^3 sigma+mass, N={n}, nnz={nnz}, tol=1e-10, x0=0",
+            "n": n, "nnz": nnz, "tol": 1e-10, "precond": "jacobi", "launch": cfg,
+        },
+        "iters": it["iters"],
+        "relres_true": it["relres_true"],
+        "us_per_iter": kern_s / max(it["iters"], 1) * 1e6,
+        "gflops_paper_convention": flops_iter * it["iters"] / wall / 1e9,
+        "spmv": {
+            "us": spmv_us, "gbs": sb / spmv_us / 1e3, "frac_hbm_peak": sb / spmv_us / 1e3 / HBM_PEAK_GBS,
+            "cold_us_median": statistics.median(cold), "cold_gbs": sb / statistics.median(cold) / 1e3,
+            "bytes": sb, "lanes_per_row": cfg["spmv_lanes"],
+        },
+        "roofline": {
+            "kernel": "pcg_solve_kernel (persistent, one launch per solve)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": sbytes, "launch_s": kern_s,
+        },
+        "paper_context": {"opencl_1gpu_tesla_t10_s": 0.659, "matlab_core2duo_s": 3.17,
+                          "note": "different (unavailable) matrix and hardware; context only"},
+    }
+
+    if not args.no_cpu:
+        import oracle
+
+        reps = 2
+        log(f"cpu baseline: {reps} oracle solves")
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            xo, io = oracle.pcg(a, b, tol=1e-10)
+            ts.append(time.perf_counter() - t)
+        out["cpu_baseline"] = {
+            "value": statistics.mean(ts), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full FP64 Jacobi-PCG solves of the same {args.n}^3 system "
+                      f"({io['iters']} iterations each), single-threaded C, {cpu_model()}",
+            "iters": io["iters"],
+        }
+        out["gpu_vs_oracle_solution_relerr"] = float(
+            np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * jpcg -- Jacobi-preconditioned conjugate gradients for CSR finite-element
+ * systems on AMD MI355X (gfx950).
+ *
+ * The operation is the one the paper parallelises (Section IV): the conjugate-
+ * gradient method for a symmetric positive-definite matrix stored in CSR, run
+ * to a relative residual of 1e-10 (Table I caption) within at most N
+ * iterations.  Its repetitive work -- the sparse matrix-vector product the
+ * paper calls "DGEMV(sparse)" and the vector updates and dot products around
+ * it -- runs in hand-written HIP kernels.  The scalar steps the paper kept on
+ * the host (alpha, beta, the continue-condition) stay on the device here.
+ *
+ * Conventions for every call:
+ *   - Matrices are square CSR: int32 rowptr[n+1] (rowptr[0] = 0, non-
+ *     decreasing, rowptr[n] = nnz), int32 col[nnz] in [0, n), float64
+ *     val[nnz].  Columns need not be sorted; the Jacobi preconditioner needs
+ *     every diagonal entry present and positive.
+ *   - Vectors passed to solve/apply calls are DEVICE pointers on the
+ *     context's device; matrices passed to create calls may be host or
+ *     device memory (cg_csr.mem).  The library copies matrices into memory it
+ *     owns, so the caller may free its arrays once create returns.
+ *   - Work is enqueued on the HIP stream given at create.  Calls that return
+ *     a status (solves) synchronise that stream before returning; calls that
+ *     only compute (spmv, spmm) return after enqueueing.
+ *   - Return codes: >= 0 is a solver status (CG_CONVERGED, CG_MAXIT,
+ *     CG_BREAKDOWN); < 0 is an API error, with text from cg_strerror() and,
+ *     where a context exists, detail from cg_last_error().
+ *   - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef JPCG_H
+#define JPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Solver statuses (>= 0) and API errors (< 0). */
+enum {
+    CG_CONVERGED = 0,    /* ||b - A x|| <= tol ||b||, confirmed on the true residual  */
+    CG_MAXIT = 1,        /* maxit iterations done; x holds the last iterate          */
+    CG_BREAKDOWN = 2,    /* p'Ap <= 0, r'z <= 0 or a non-finite scalar: not SPD / NaN */
+    CG_EINVAL = -1,      /* bad argument or malformed CSR                            */
+    CG_EDIAG = -2,       /* Jacobi requested but a diagonal entry is missing or <= 0 */
+    CG_ENOMEM = -3,      /* device or host allocation failed                         */
+    CG_EHIP = -4,        /* a HIP runtime call failed                                */
+    CG_ETIMEOUT = -5,    /* a device-side wait exceeded its limit; the kernel left   */
+    CG_EUNSUPPORTED = -6 /* option not available for this context                    */
+};
+
+enum { CG_MEM_HOST = 0, CG_MEM_DEVICE = 1 };
+/* Preconditioner choice; 0 in cg_opts.precond selects the default (Jacobi). */
+enum { CG_PRECOND_DEFAULT = 0, CG_PRECOND_JACOBI = 1, CG_PRECOND_NONE = 2 };
+
+/* A square CSR matrix (see the conventions above). */
+typedef struct {
+    int32_t n;
+    int32_t mem; /* CG_MEM_HOST or CG_MEM_DEVICE */
+    int64_t nnz;
+    const int32_t *rowptr;
+    const int32_t *col;
+    const double *val;
+} cg_csr;
+
+/* Options for cg_create.  Zero-initialised fields take the defaults. */
+typedef struct {
+    int32_t precond;       /* CG_PRECOND_JACOBI (default) or CG_PRECOND_NONE (M = I)    */
+    int32_t fp32_copy;     /* 1: also keep an FP32 copy of the values (mixed form)       */
+    int32_t autotune;      /* 1: time launch shapes at create and keep the fastest       */
+    int32_t lanes_per_row; /* 0 = default; else 4, 8, 16, 32 or 64 lanes per CSR row      */
+    int32_t blocks_per_cu; /* 0 = default; persistent-grid workgroups per compute unit  */
+    int32_t history;       /* 1: record ||r_k|| / ||b|| for every iteration            */
+    int32_t reserved[10];
+} cg_opts;
+
+/* Result of a solve. */
+typedef struct {
+    int32_t iters;        /* products A p inside the CG loop                          */
+    int32_t status;       /* CG_CONVERGED, CG_MAXIT, CG_BREAKDOWN or an API error     */
+    int32_t replacements; /* times r was replaced by the true residual                */
+    int32_t outer;        /* refinement steps (mixed-precision form), else 0          */
+    double relres_recur;  /* ||r_k|| / ||b|| from the recurrence at exit             */
+    double relres_true;   /* ||b - A x|| / ||b|| of the returned x, in FP64           */
+    double seconds;       /* device time of the solve, HIP events around the kernels */
+} cg_info;
+
+/* The launch shape a context uses (after autotuning, if requested). */
+typedef struct {
+    int32_t lanes_per_row;
+    int32_t block_size;
+    int32_t grid;          /* workgroups of the persistent solver grid            */
+    int32_t spmv_lanes;    /* lanes per row of the standalone spmv                */
+    double spmv_us;        /* autotuner's best spmv time, 0 if not tuned          */
+    double iter_us;        /* autotuner's best solver time per iteration, or 0    */
+} cg_config;
+
+typedef struct cg_ctx cg_ctx;
+
+/* Fill *opts with defaults: Jacobi, no FP32 copy, no autotune, no history. */
+void cg_opts_default(cg_opts *opts);
+
+/*
+ * Create a solver context for A on the current HIP device (Section IV: the
+ * setup step that reads the CSR data and prepares the loop).
+ *   A          : the matrix; copied, validated (rowptr monotone, rowptr[0]=0,
+ *                rowptr[n]=nnz, 0 <= col < n, nnz < 2^31), then the Jacobi
+ *                inverse diagonal is extracted on the device.
+ *   opts       : NULL for defaults.
+ *   hip_stream : a hipStream_t (NULL = the null stream), e.g. torch's
+ *                torch.cuda.current_stream().cuda_stream.
+ *   out        : receives the context; free it with cg_destroy.
+ * Returns 0, CG_EINVAL, CG_EDIAG, CG_ENOMEM or CG_EHIP.  On error *out is NULL.
+ */
+int cg_create(const cg_csr *A, const cg_opts *opts, void *hip_stream, cg_ctx **out);
+
+/*
+ * Solve A x = b by Jacobi-preconditioned CG (Section IV; tolerance as in the
+ * Table I caption).  b and x are device pointers to float64[n]; x holds x0 on
+ * entry (zero it for the default start) and the result on exit; x must not
+ * alias b.  Stops when the recurrence residual satisfies ||r|| <= tol ||b||
+ * and the true residual b - A x confirms it (otherwise r is replaced by the
+ * true residual and the loop continues).  maxit <= 0 means n.  ||b|| = 0
+ * gives x = 0 and 0 iterations.  The whole loop runs in one persistent
+ * kernel launch; the call synchronises the context's stream.
+ * info may be NULL.  Returns the status (>= 0) or an API error (< 0).
+ */
+int cg_solve(cg_ctx *ctx, const double *b, double *x, double tol, int32_t maxit, cg_info *info);
+
+/* y = A x (the paper's "DGEMV(sparse)").  Device pointers to float64[n], x != y.
+ * Asynchronous on the context's stream.  Returns 0 or an API error. */
+int spmv(cg_ctx *ctx, const double *x, double *y);
+
+/* Copy up to `cap` entries of the last solve's residual history
+ * (||r_k|| / ||b||, k = 0..iters) into host memory; returns the count
+ * written, or an API error if history was not enabled at create. */
+int cg_get_history(cg_ctx *ctx, double *host_out, int32_t cap);
+
+/* The launch shape in use. */
+int cg_get_config(cg_ctx *ctx, cg_config *cfg);
+
+/* Free the context and all device memory it owns.  NULL is ignored. */
+void cg_destroy(cg_ctx *ctx);
+
+/* Static text for a status or error code. */
+const char *cg_strerror(int code);
+
+/* Detail of the last error on this context ("" if none). */
+const char *cg_last_error(const cg_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JPCG_H */

@@ -1,0 +1,171 @@
+// Device and host helpers shared by the solver kernels (gfx950, wave64).
+//
+// Everything reduces in a fixed order: a wave reduces with an xor butterfly
+// (IEEE addition is commutative, so every lane ends with the same bits), a
+// block adds its waves in index order, and a grid reduction adds per-block
+// partials in a fixed strided order followed by the same block reduction.
+// Repeated runs with the same launch shape are therefore bitwise identical,
+// and every block of a persistent grid obtains the same scalar, which keeps
+// the control flow of all blocks in step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/jpcg.h"
+
+namespace jpcg {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Reductions
+// ---------------------------------------------------------------------------
+template <int WIDTH, typename T>
+__device__ __forceinline__ T group_sum(T v)
+{
+    // Butterfly within aligned groups of WIDTH lanes (WIDTH a power of two <= 64).
+#pragma unroll
+    for (int off = WIDTH / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Sum K values over the block; the totals are returned in every thread.
+// `lds` must hold (BS / 64) * K doubles.
+template <int BS, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* lds)
+{
+    constexpr int NW = BS / kWave;
+    const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = group_sum<kWave>(v[k]);
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[w * K + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) s += lds[j * K + k];
+        v[k] = s;
+    }
+}
+
+// Write the block's K partial sums to part[k * stride + slot].
+template <int BS, int K>
+__device__ __forceinline__ void block_partials(double (&v)[K], double* lds, double* part, int stride, int slot)
+{
+    block_sum<BS, K>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[k * stride + slot] = v[k];
+    }
+}
+
+// Every block reduces the G partials of K quantities in the same order.
+template <int BS, int K>
+__device__ __forceinline__ void grid_sum(const double* part, int stride, int G, double (&out)[K], double* lds)
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int j = threadIdx.x; j < G; j += BS) s += part[k * stride + j];
+        out[k] = s;
+    }
+    block_sum<BS, K>(out, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Grid barrier for co-resident (cooperatively launched) grids.
+//
+// Sense by generation: each arriving block adds one to `count`; the last one
+// resets `count` and advances `gen`; the others spin on `gen`.  Thread 0 of a
+// block fences at agent scope before arriving (publishing the block's writes
+// to all XCDs) and after leaving (so later loads observe other blocks'
+// writes).  Every wait is bounded by a wall-clock limit: on expiry the block
+// raises `abort`, and every waiter that sees `abort` leaves, so all waves
+// exit even if a block never arrives.
+// ---------------------------------------------------------------------------
+struct alignas(256) GridBarrier {
+    unsigned count;
+    unsigned pad0[63];
+    unsigned gen;
+    unsigned pad1[63];
+    unsigned abort;
+    unsigned pad2[63];
+};
+
+__device__ __forceinline__ unsigned barrier_gen(GridBarrier* gb)
+{
+    return __hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Returns false if the barrier was abandoned.  `gen` is the block's copy of
+// the generation counter; it is advanced on success.
+__device__ __forceinline__ bool grid_barrier(GridBarrier* gb, unsigned nblocks, unsigned& gen,
+                                             long long limit_ticks, int* s_flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        unsigned prev = __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == nblocks - 1) {
+            __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&gb->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const long long t0 = wall_clock64();
+            while (__hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (__hip_atomic_load(&gb->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() - t0 > limit_ticks) {
+                    __hip_atomic_store(&gb->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+        *s_flag = ok;
+    }
+    __syncthreads();
+    const bool ok = *s_flag != 0;
+    gen += 1;
+    __syncthreads();  // s_flag may be rewritten by the next barrier
+    return ok;
+}
+
+// Map the hardware block index to a logical one so that the blocks that land
+// on one XCD (dispatched round-robin, block b on XCD b % 8) own a contiguous
+// range of rows and share gathered vector entries in that XCD's L2.
+__device__ __forceinline__ int xcd_logical_block(int b, int G)
+{
+    constexpr int kXcd = 8;
+    if (G % kXcd != 0) return b;
+    return (b % kXcd) * (G / kXcd) + b / kXcd;
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+struct HipError {
+    hipError_t code;
+    const char* what;
+};
+
+#define JPCG_HIP(call)                                             \
+    do {                                                           \
+        hipError_t e_ = (call);                                    \
+        if (e_ != hipSuccess) throw ::jpcg::HipError{e_, #call};   \
+    } while (0)
+
+}  // namespace jpcg

@@ -1,0 +1,309 @@
+// The steps of one Jacobi-PCG solve, as device functions over a block's rows.
+//
+// A "team" is a set of co-resident workgroups that owns one system: each
+// workgroup owns a contiguous row range [rs, re) (balanced by nonzeros on the
+// host) and the team meets at grid barriers between steps.  The single-system
+// solver runs one team made of the whole grid; the batched solver runs many
+// teams in one launch.  A team of one workgroup synchronises with
+// __syncthreads alone.
+//
+// Per iteration there are two team-wide reductions, so two barriers:
+//   step A   q = A p_new, p_new = z + beta p_old formed on the fly (the direction
+//            update of the previous iteration is fused into the gather), and the
+//            partial of sigma = p_new' q;
+//   step B   x += alpha p_new, r -= alpha q, z = M^-1 r, partials of r'z and r'r.
+// The continue-condition and the true-residual confirmation (step R,
+// r = b - A x) follow the paper's loop-with-constraint structure (Section IV).
+//
+// Value type T is double (FP64 solve) or float (inner solve of the mixed-
+// precision form).  Dot products always accumulate in double.
+#pragma once
+
+#include "common.hpp"
+
+namespace jpcg {
+
+// Slots of the partial-sum array, each `G` doubles long.  A group of K
+// consecutive slots holds the K quantities of one reduction.
+enum : int {
+    SLOT_SIG = 0,    // p'q
+    SLOT_ITER = 1,   // r'z, r'r after step B
+    SLOT_SETUP = 3,  // r'r, r'z, b'b of the initial residual
+    SLOT_CHECK = 6,  // r'r, r'z of the confirming true residual
+    NSLOT = 8
+};
+
+// Device-side result of a solve, copied back by the host.
+struct DevInfo {
+    int iters;
+    int status;
+    int replacements;
+    int outer;
+    double rr_recur;  // ||r||^2 of the recurrence at exit
+    double rr_true;   // ||b - A x||^2 of the returned x
+    double bb;        // ||b||^2
+    double pad;
+};
+
+template <typename T>
+struct SysView {
+    int n;
+    const int* __restrict__ rowptr;
+    const int* __restrict__ col;
+    const T* __restrict__ val;
+    const T* __restrict__ dinv;  // M^-1 diagonal (all ones for no preconditioner)
+    const T* b;
+    T* x;
+    T* r;
+    T* z;
+    T* p0;
+    T* p1;
+    T* q;
+};
+
+struct Team {
+    GridBarrier* bar;
+    double* part;  // NSLOT * G doubles
+    int G;         // workgroups in the team
+    int L;         // this workgroup's index in the team
+    unsigned gen;  // thread 0's copy of the barrier generation
+    long long limit;
+    int* s_flag;   // LDS word used by the barrier
+
+    __device__ __forceinline__ bool sync()
+    {
+        if (G == 1) {
+            __syncthreads();
+            return true;
+        }
+        return grid_barrier(bar, (unsigned)G, gen, limit, s_flag);
+    }
+    __device__ __forceinline__ double* slot(int s) const { return part + (size_t)s * G; }
+};
+
+template <typename T>
+__device__ __forceinline__ T fma_t(T a, T b, T c)
+{
+    return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fma_t<float>(float a, float b, float c)
+{
+    return __builtin_fmaf(a, b, c);
+}
+
+// Step A: p_new = z + beta p_old (or z on the first step), q = A p_new.
+// Returns this thread's share of p_new' q.
+template <int LPR, int BS, typename T>
+__device__ __forceinline__ double step_a(const SysView<T>& s, int rs, int re, bool first, T beta,
+                                         const T* __restrict__ pold, T* __restrict__ pnew)
+{
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    constexpr int GPB = BS / LPR;
+    const T* __restrict__ z = s.z;
+    double sig = 0.0;
+    for (int i0 = rs; i0 < re; i0 += GPB) {
+        const int i = i0 + grp;
+        T acc = T(0);
+        if (i < re) {
+            const int k1 = s.rowptr[i + 1];
+            if (first) {
+                for (int k = s.rowptr[i] + lane; k < k1; k += LPR) acc = fma_t(s.val[k], z[s.col[k]], acc);
+            } else {
+                for (int k = s.rowptr[i] + lane; k < k1; k += LPR) {
+                    const int j = s.col[k];
+                    acc = fma_t(s.val[k], fma_t(beta, pold[j], z[j]), acc);
+                }
+            }
+        }
+        acc = group_sum<LPR>(acc);
+        if (lane == 0 && i < re) {
+            const T pi = first ? z[i] : fma_t(beta, pold[i], z[i]);
+            pnew[i] = pi;
+            s.q[i] = acc;
+            sig += (double)pi * (double)acc;
+        }
+    }
+    return sig;
+}
+
+// Step B: x += alpha p, r -= alpha q, z = M^-1 r; shares of r'z and r'r.
+template <int BS, typename T>
+__device__ __forceinline__ void step_b(const SysView<T>& s, int rs, int re, T alpha, const T* __restrict__ p,
+                                       double& rz, double& rr)
+{
+    for (int i = rs + (int)threadIdx.x; i < re; i += BS) {
+        const T pi = p[i], qi = s.q[i];
+        s.x[i] = fma_t(alpha, pi, s.x[i]);
+        const T ri = fma_t(-alpha, qi, s.r[i]);
+        s.r[i] = ri;
+        const T zi = s.dinv[i] * ri;
+        s.z[i] = zi;
+        rz += (double)ri * (double)zi;
+        rr += (double)ri * (double)ri;
+    }
+}
+
+// Step R: rout = b - A x and, if zout, zout = M^-1 rout; shares of r'r, r'z, b'b.
+template <int LPR, int BS, typename T>
+__device__ __forceinline__ void step_r(const SysView<T>& s, int rs, int re, T* __restrict__ rout,
+                                       T* __restrict__ zout, double& rr, double& rz, double& bb)
+{
+    const int lane = threadIdx.x & (LPR - 1);
+    const int grp = threadIdx.x / LPR;
+    constexpr int GPB = BS / LPR;
+    const T* __restrict__ x = s.x;
+    for (int i0 = rs; i0 < re; i0 += GPB) {
+        const int i = i0 + grp;
+        T acc = T(0);
+        if (i < re) {
+            const int k1 = s.rowptr[i + 1];
+            for (int k = s.rowptr[i] + lane; k < k1; k += LPR) acc = fma_t(s.val[k], x[s.col[k]], acc);
+        }
+        acc = group_sum<LPR>(acc);
+        if (lane == 0 && i < re) {
+            const T bi = s.b[i];
+            const T ri = bi - acc;
+            rout[i] = ri;
+            rr += (double)ri * (double)ri;
+            bb += (double)bi * (double)bi;
+            if (zout) {
+                const T zi = s.dinv[i] * ri;
+                zout[i] = zi;
+                rz += (double)ri * (double)zi;
+            }
+        }
+    }
+}
+
+// One full Jacobi-PCG solve of system s by team t, following the loop of the
+// FP64 oracle step for step (residual replacement included).  Every decision
+// is taken on team-reduced scalars that are bitwise identical in every
+// workgroup, so all workgroups leave the loop together.  Returns the status;
+// workgroup 0 of the team writes *info (and hist[k] = ||r_k|| / ||b||).
+template <int LPR, int BS, typename T>
+__device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol, int maxit, double* lds,
+                        DevInfo* info, double* hist)
+{
+    const bool writer = (t.L == 0 && threadIdx.x == 0);
+    int status = CG_MAXIT, k = 0, repl = 0;
+    double nb = 0.0, rr = 0.0, rrt = -1.0;
+
+    {   // r0 = b - A x0, z0 = M^-1 r0, ||b||^2, ||r0||^2, r0'z0
+        double v[3] = {0.0, 0.0, 0.0};
+        step_r<LPR, BS, T>(s, rs, re, s.r, s.z, v[0], v[1], v[2]);
+        block_partials<BS, 3>(v, lds, t.slot(SLOT_SETUP), t.G, t.L);
+    }
+    if (!t.sync()) return CG_ETIMEOUT;
+    double rho;
+    {
+        double g[3];
+        grid_sum<BS, 3>(t.slot(SLOT_SETUP), t.G, t.G, g, lds);
+        rr = g[0];
+        rho = g[1];
+        nb = sqrt(g[2]);
+        if (writer) info->bb = g[2];
+    }
+    if (nb == 0.0) {
+        for (int i = rs + (int)threadIdx.x; i < re; i += BS) s.x[i] = T(0);
+        if (writer) {
+            *info = DevInfo{0, CG_CONVERGED, 0, 0, 0.0, 0.0, 0.0, 0.0};
+            if (hist) hist[0] = 0.0;
+        }
+        return CG_CONVERGED;
+    }
+    const double thr = tol * nb;
+    if (writer && hist) hist[0] = sqrt(rr) / nb;
+    if (sqrt(rr) <= thr) {
+        if (writer) {
+            info->iters = 0;
+            info->status = CG_CONVERGED;
+            info->replacements = 0;
+            info->rr_recur = rr;
+            info->rr_true = rr;
+        }
+        return CG_CONVERGED;
+    }
+
+    double beta = 0.0;
+    while (k < maxit) {
+        const T* pold = (k & 1) ? s.p1 : s.p0;
+        T* pnew = (k & 1) ? s.p0 : s.p1;
+        {
+            double v[1] = {step_a<LPR, BS, T>(s, rs, re, k == 0, (T)beta, pold, pnew)};
+            block_partials<BS, 1>(v, lds, t.slot(SLOT_SIG), t.G, t.L);
+        }
+        if (!t.sync()) return CG_ETIMEOUT;
+        double sigma;
+        {
+            double g[1];
+            grid_sum<BS, 1>(t.slot(SLOT_SIG), t.G, t.G, g, lds);
+            sigma = g[0];
+        }
+        if (!(sigma > 0.0) || !isfinite(sigma)) {
+            status = CG_BREAKDOWN;
+            break;
+        }
+        const double alpha = rho / sigma;
+        {
+            double v[2] = {0.0, 0.0};
+            step_b<BS, T>(s, rs, re, (T)alpha, pnew, v[0], v[1]);
+            block_partials<BS, 2>(v, lds, t.slot(SLOT_ITER), t.G, t.L);
+        }
+        ++k;
+        if (!t.sync()) return CG_ETIMEOUT;
+        double rz;
+        {
+            double g[2];
+            grid_sum<BS, 2>(t.slot(SLOT_ITER), t.G, t.G, g, lds);
+            rz = g[0];
+            rr = g[1];
+        }
+        if (writer && hist) hist[k] = sqrt(rr) / nb;
+        if (sqrt(rr) <= thr) {
+            // Continue-condition met on the recurrence: confirm on b - A x.
+            {
+                double v[2] = {0.0, 0.0}, unused = 0.0;
+                step_r<LPR, BS, T>(s, rs, re, s.r, s.z, v[0], v[1], unused);
+                block_partials<BS, 2>(v, lds, t.slot(SLOT_CHECK), t.G, t.L);
+            }
+            if (!t.sync()) return CG_ETIMEOUT;
+            double g[2];
+            grid_sum<BS, 2>(t.slot(SLOT_CHECK), t.G, t.G, g, lds);
+            if (sqrt(g[0]) <= thr) {
+                status = CG_CONVERGED;
+                rrt = g[0];
+                break;
+            }
+            ++repl;  // r and z now hold the true residual and its preconditioned form
+            rz = g[1];
+        }
+        if (!(rz > 0.0) || !isfinite(rz)) {
+            status = CG_BREAKDOWN;
+            break;
+        }
+        beta = rz / rho;
+        rho = rz;
+    }
+
+    if (rrt < 0.0) {  // report the true residual of the returned x
+        double v[1] = {0.0}, unused0 = 0.0, unused1 = 0.0;
+        step_r<LPR, BS, T>(s, rs, re, s.q, (T*)nullptr, v[0], unused0, unused1);
+        block_partials<BS, 1>(v, lds, t.slot(SLOT_CHECK), t.G, t.L);
+        if (!t.sync()) return CG_ETIMEOUT;
+        double g[1];
+        grid_sum<BS, 1>(t.slot(SLOT_CHECK), t.G, t.G, g, lds);
+        rrt = g[0];
+    }
+    if (writer) {
+        info->iters = k;
+        info->status = status;
+        info->replacements = repl;
+        info->rr_recur = rr;
+        info->rr_true = rrt;
+    }
+    return status;
+}
+
+}  // namespace jpcg

@@ -1,0 +1,143 @@
+"""Python face of the C-ABI: torch supplies device memory and the stream.
+
+Names follow the C calls (cg_create / cg_solve / spmv).  Nothing here
+computes: each method validates and marshals its arguments, then calls the
+HIP library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import capi
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _as_device_vec(t, n, name, dtype=None):
+    torch = _torch()
+    dtype = dtype or torch.float64
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if t.dtype != dtype or t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor with {n} entries")
+    return t
+
+
+def make_csr(a) -> tuple[capi.cg_csr, list]:
+    """cg_csr for a matrix given as an object with n/rowptr/col/val (numpy or torch)."""
+    torch = _torch()
+    keep = []
+    if isinstance(a.rowptr, torch.Tensor) and a.rowptr.is_cuda:
+        if a.rowptr.numel() != int(a.n) + 1 or a.val.numel() != a.col.numel():
+            raise ValueError("rowptr must have n + 1 entries and val as many as col")
+        rowptr = a.rowptr.to(torch.int32).contiguous()
+        col = a.col.to(torch.int32).contiguous()
+        val = a.val.to(torch.float64).contiguous()
+        keep += [rowptr, col, val]
+        csr = capi.cg_csr(int(a.n), capi.CG_MEM_DEVICE, int(col.numel()), rowptr.data_ptr(),
+                          col.data_ptr(), val.data_ptr())
+    else:
+        rowptr = np.ascontiguousarray(a.rowptr, dtype=np.int32)
+        col = np.ascontiguousarray(a.col, dtype=np.int32)
+        val = np.ascontiguousarray(a.val, dtype=np.float64)
+        keep += [rowptr, col, val]
+        if val.size != col.size:
+            raise ValueError("val must have as many entries as col")
+        if rowptr.size != int(a.n) + 1:
+            raise ValueError("rowptr must have n + 1 entries")
+        csr = capi.cg_csr(int(a.n), capi.CG_MEM_HOST, int(col.size), rowptr.ctypes.data, col.ctypes.data,
+                          val.ctypes.data)
+    return csr, keep
+
+
+def make_opts(precond="jacobi", fp32_copy=False, autotune=False, lanes_per_row=0, blocks_per_cu=0,
+              history=False) -> capi.cg_opts:
+    o = capi.cg_opts()
+    capi.load().cg_opts_default(ctypes.byref(o))
+    o.precond = {"jacobi": capi.CG_PRECOND_JACOBI, "none": capi.CG_PRECOND_NONE}[precond]
+    o.fp32_copy = int(bool(fp32_copy))
+    o.autotune = int(bool(autotune))
+    o.lanes_per_row = int(lanes_per_row)
+    o.blocks_per_cu = int(blocks_per_cu)
+    o.history = int(bool(history))
+    return o
+
+
+class Solver:
+    """A cg_ctx: one SPD CSR matrix resident on the GPU."""
+
+    def __init__(self, a, precond="jacobi", fp32_copy=False, autotune=False, lanes_per_row=0,
+                 blocks_per_cu=0, history=False, stream=None):
+        torch = _torch()
+        self._lib = capi.load()
+        self.n = int(a.n)
+        self.nnz = int(a.rowptr[-1])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        csr, _keep = make_csr(a)
+        opts = make_opts(precond, fp32_copy, autotune, lanes_per_row, blocks_per_cu, history)
+        ctx = ctypes.c_void_p()
+        rc = self._lib.cg_create(ctypes.byref(csr), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(ctx))
+        capi.check(rc)
+        self.ctx = ctx
+        self.history_enabled = bool(history)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self._lib.cg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- the three calls of the path ------------------------------------------------
+    def cg_solve(self, b, x, tol=1e-10, maxit=0) -> dict:
+        """In-place solve: x holds x0 on entry, the solution on exit."""
+        _as_device_vec(b, self.n, "b")
+        _as_device_vec(x, self.n, "x")
+        info = capi.cg_info()
+        rc = self._lib.cg_solve(self.ctx, b.data_ptr(), x.data_ptr(), float(tol), int(maxit), ctypes.byref(info))
+        capi.check(rc, self.ctx)
+        return info.as_dict()
+
+    def solve(self, b, x0=None, tol=1e-10, maxit=0):
+        torch = _torch()
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        info = self.cg_solve(b, x, tol, maxit)
+        return x, info
+
+    def spmv(self, x, y=None):
+        torch = _torch()
+        _as_device_vec(x, self.n, "x")
+        if y is None:
+            y = torch.empty_like(x)
+        _as_device_vec(y, self.n, "y")
+        capi.check(self._lib.spmv(self.ctx, x.data_ptr(), y.data_ptr()), self.ctx)
+        return y
+
+    # -- introspection -------------------------------------------------------------
+    def history(self) -> np.ndarray:
+        cap = self.n + 1
+        buf = np.empty(cap)
+        m = capi.check(self._lib.cg_get_history(self.ctx, buf.ctypes.data, cap), self.ctx)
+        return buf[:m].copy()
+
+    def config(self) -> dict:
+        c = capi.cg_config()
+        capi.check(self._lib.cg_get_config(self.ctx, ctypes.byref(c)), self.ctx)
+        return c.as_dict()
