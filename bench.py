@@ -158,10 +158,10 @@ def main():
         "spmv": {
             "us": spmv_us, "gbs": sb / spmv_us / 1e3, "frac_hbm_peak": sb / spmv_us / 1e3 / HBM_PEAK_GBS,
             "cold_us_median": statistics.median(cold), "cold_gbs": sb / statistics.median(cold) / 1e3,
-            "bytes": sb, "lanes_per_row": cfg["spmv_lanes"],
+            "bytes": sb, "nnz_per_lane": cfg["nnz_per_lane"],
         },
         "roofline": {
-            "kernel": "pcg_solve_kernel (persistent, one launch per solve)",
+            "kernel": "whole solve (k_direction + k_update per iteration, hipGraph chunks)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
             "bytes_per_launch": sbytes, "launch_s": kern_s,

@@ -68,10 +68,12 @@ typedef struct {
     int32_t precond;       /* CG_PRECOND_JACOBI (default) or CG_PRECOND_NONE (M = I)    */
     int32_t fp32_copy;     /* 1: also keep an FP32 copy of the values (mixed form)       */
     int32_t autotune;      /* 1: time launch shapes at create and keep the fastest       */
-    int32_t lanes_per_row; /* 0 = default; else 4, 8, 16, 32 or 64 lanes per CSR row      */
+    int32_t nnz_per_lane;  /* 0 = default; else 4, 8 or 16: a product tile holds 64x that */
     int32_t blocks_per_cu; /* 0 = default; persistent-grid workgroups per compute unit  */
     int32_t history;       /* 1: record ||r_k|| / ||b|| for every iteration            */
-    int32_t reserved[10];
+    int32_t block_size;    /* 0 = default; else 256, 512 or 1024 threads per workgroup  */
+    int32_t chunk;         /* 0 = default; CG iterations per launched hipGraph chunk    */
+    int32_t reserved[8];
 } cg_opts;
 
 /* Result of a solve. */
@@ -87,10 +89,12 @@ typedef struct {
 
 /* The launch shape a context uses (after autotuning, if requested). */
 typedef struct {
-    int32_t lanes_per_row;
+    int32_t nnz_per_lane;  /* a product tile holds up to 64 * nnz_per_lane nonzeros */
     int32_t block_size;
-    int32_t grid;          /* workgroups of the persistent solver grid            */
-    int32_t spmv_lanes;    /* lanes per row of the standalone spmv                */
+    int32_t grid;          /* workgroups of every solver kernel and of spmv       */
+    int32_t tiles;         /* product tiles (runs of whole rows) of the matrix    */
+    int32_t chunk;         /* iterations per hipGraph chunk                       */
+    int32_t pad;
     double spmv_us;        /* autotuner's best spmv time, 0 if not tuned          */
     double iter_us;        /* autotuner's best solver time per iteration, or 0    */
 } cg_config;
@@ -121,8 +125,9 @@ int cg_create(const cg_csr *A, const cg_opts *opts, void *hip_stream, cg_ctx **o
  * alias b.  Stops when the recurrence residual satisfies ||r|| <= tol ||b||
  * and the true residual b - A x confirms it (otherwise r is replaced by the
  * true residual and the loop continues).  maxit <= 0 means n.  ||b|| = 0
- * gives x = 0 and 0 iterations.  The whole loop runs in one persistent
- * kernel launch; the call synchronises the context's stream.
+ * gives x = 0 and 0 iterations.  Iterations run as two kernels each,
+ * launched in hipGraph chunks; every scalar stays on the device.  The call
+ * synchronises the context's stream.
  * info may be NULL.  Returns the status (>= 0) or an API error (< 0).
  */
 int cg_solve(cg_ctx *ctx, const double *b, double *x, double tol, int32_t maxit, cg_info *info);

@@ -5,8 +5,8 @@
 // block adds its waves in index order, and a grid reduction adds per-block
 // partials in a fixed strided order followed by the same block reduction.
 // Repeated runs with the same launch shape are therefore bitwise identical,
-// and every block of a persistent grid obtains the same scalar, which keeps
-// the control flow of all blocks in step.
+// and every block that reduces the same partials obtains the same scalar,
+// which keeps the control flow of all blocks in step.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,28 +57,49 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* lds)
     }
 }
 
-// Write the block's K partial sums to part[k * stride + slot].
+// Write the block's K partial sums to part[slot * K + k] (interleaved, so a
+// reader fetches one block's K values with one vector load).
 template <int BS, int K>
-__device__ __forceinline__ void block_partials(double (&v)[K], double* lds, double* part, int stride, int slot)
+__device__ __forceinline__ void block_partials(double (&v)[K], double* lds, double* part, int slot)
 {
     block_sum<BS, K>(v, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) part[k * stride + slot] = v[k];
+        for (int k = 0; k < K; ++k) part[slot * K + k] = v[k];
     }
 }
 
-// Every block reduces the G partials of K quantities in the same order.
+// Every block reduces the G interleaved K-tuples of partials in the same
+// order, so every block obtains the same bits.
 template <int BS, int K>
-__device__ __forceinline__ void grid_sum(const double* part, int stride, int G, double (&out)[K], double* lds)
+__device__ __forceinline__ void grid_sum(const double* part, int G, double (&out)[K], double* lds)
 {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int j = threadIdx.x; j < G; j += BS) s += part[k * stride + j];
-        out[k] = s;
+    for (int k = 0; k < K; ++k) out[k] = 0.0;
+    for (int j = threadIdx.x; j < G; j += BS) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] += part[j * K + k];
     }
     block_sum<BS, K>(out, lds);
+}
+
+// Every WAVE reduces the G interleaved K-tuples itself: lane l adds entries
+// l, l+64, ... in order, then an xor butterfly gives every lane the same
+// bits.  No LDS and no workgroup barrier, so the loads can overlap other work
+// issued before the first use of the result.
+template <int K>
+__device__ __forceinline__ void wave_grid_sum(const double* __restrict__ part, int G, double (&out)[K])
+{
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = 0.0;
+#pragma unroll 4
+    for (int j = lane; j < G; j += kWave) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] += part[j * K + k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = group_sum<kWave>(out[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -107,21 +128,26 @@ __device__ __forceinline__ unsigned barrier_gen(GridBarrier* gb)
 }
 
 // Returns false if the barrier was abandoned.  `gen` is the block's copy of
-// the generation counter; it is advanced on success.
+// the generation counter; it is advanced on success.  Ordering: a release
+// fence before arriving, relaxed atomics and a relaxed spin (an acquiring
+// load would invalidate caches on every poll), an acquire-release fence in
+// the last arriver before it advances `gen`, and an acquire fence after the
+// wait.
 __device__ __forceinline__ bool grid_barrier(GridBarrier* gb, unsigned nblocks, unsigned& gen,
                                              long long limit_ticks, int* s_flag)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        __threadfence();
-        unsigned prev = __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        unsigned prev = __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == nblocks - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&gb->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&gb->gen, gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const long long t0 = wall_clock64();
-            while (__hip_atomic_load(&gb->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+            while (__hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
                 __builtin_amdgcn_s_sleep(1);
                 if (__hip_atomic_load(&gb->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                     ok = 0;
@@ -134,7 +160,7 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier* gb, unsigned nblocks, 
                 }
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_flag = ok;
     }
     __syncthreads();

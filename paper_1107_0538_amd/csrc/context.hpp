@@ -30,14 +30,8 @@ struct cg_ctx {
     double* p1 = nullptr;
     double* q = nullptr;
 
-    // Persistent-grid state.
-    double* part = nullptr;  // NSLOT * grid_cap
-    int* blk_row = nullptr;  // grid_cap + 1
-    int grid_cap = 0;
-    int blk_row_grid = 0;    // grid the current blk_row was built for
-    jpcg::GridBarrier* bar = nullptr;
-    jpcg::DevInfo* dinfo = nullptr;
-    jpcg::DevInfo* hinfo = nullptr;  // pinned
+    // Graph-chunked solver for the chosen launch shape.
+    struct cg_graphs* graphs = nullptr;
     double* hist = nullptr;
     int hist_cap = 0;
     int hist_len = 0;
@@ -47,9 +41,10 @@ struct cg_ctx {
     long long limit_ticks = 0;
 
     // Launch shape.
-    int lpr = 32;
-    int spmv_lpr = 32;
+    int npl = 8;   // nonzeros per lane of a product tile
+    int bs = 512;
     int grid = 0;
+    int chunk = 16;
     double tuned_spmv_us = 0.0;
     double tuned_iter_us = 0.0;
 
@@ -58,18 +53,8 @@ struct cg_ctx {
 
 namespace jpcg {
 
-// Row boundaries of G workgroups with about nnz / G nonzeros each.
+// Row boundaries of G workgroups with about (nnz + n) / G rows-plus-nonzeros each.
 void partition_rows(const std::vector<int>& rowptr, int G, std::vector<int>& out);
-
-// Ensure the context's persistent-grid buffers fit `G` workgroups and the
-// row partition matches it.
-void ensure_grid(cg_ctx* c, int G);
-
-// Largest cooperative grid for the FP64 solver at `lpr`.
-int max_coop_grid(cg_ctx* c, int lpr);
-
-// Read back the barrier's abort word; reset the barrier if it was raised.
-bool barrier_aborted(hipStream_t stream, GridBarrier* bar);
 
 int set_error(cg_ctx* c, int code, const std::string& msg);
 

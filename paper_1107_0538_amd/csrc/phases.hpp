@@ -78,6 +78,7 @@ struct Team {
         }
         return grid_barrier(bar, (unsigned)G, gen, limit, s_flag);
     }
+    // Base of reduction group s: the group's K quantities, interleaved per block.
     __device__ __forceinline__ double* slot(int s) const { return part + (size_t)s * G; }
 };
 
@@ -193,13 +194,13 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol
     {   // r0 = b - A x0, z0 = M^-1 r0, ||b||^2, ||r0||^2, r0'z0
         double v[3] = {0.0, 0.0, 0.0};
         step_r<LPR, BS, T>(s, rs, re, s.r, s.z, v[0], v[1], v[2]);
-        block_partials<BS, 3>(v, lds, t.slot(SLOT_SETUP), t.G, t.L);
+        block_partials<BS, 3>(v, lds, t.slot(SLOT_SETUP), t.L);
     }
     if (!t.sync()) return CG_ETIMEOUT;
     double rho;
     {
         double g[3];
-        grid_sum<BS, 3>(t.slot(SLOT_SETUP), t.G, t.G, g, lds);
+        grid_sum<BS, 3>(t.slot(SLOT_SETUP), t.G, g, lds);
         rr = g[0];
         rho = g[1];
         nb = sqrt(g[2]);
@@ -232,13 +233,13 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol
         T* pnew = (k & 1) ? s.p0 : s.p1;
         {
             double v[1] = {step_a<LPR, BS, T>(s, rs, re, k == 0, (T)beta, pold, pnew)};
-            block_partials<BS, 1>(v, lds, t.slot(SLOT_SIG), t.G, t.L);
+            block_partials<BS, 1>(v, lds, t.slot(SLOT_SIG), t.L);
         }
         if (!t.sync()) return CG_ETIMEOUT;
         double sigma;
         {
             double g[1];
-            grid_sum<BS, 1>(t.slot(SLOT_SIG), t.G, t.G, g, lds);
+            grid_sum<BS, 1>(t.slot(SLOT_SIG), t.G, g, lds);
             sigma = g[0];
         }
         if (!(sigma > 0.0) || !isfinite(sigma)) {
@@ -249,14 +250,14 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol
         {
             double v[2] = {0.0, 0.0};
             step_b<BS, T>(s, rs, re, (T)alpha, pnew, v[0], v[1]);
-            block_partials<BS, 2>(v, lds, t.slot(SLOT_ITER), t.G, t.L);
+            block_partials<BS, 2>(v, lds, t.slot(SLOT_ITER), t.L);
         }
         ++k;
         if (!t.sync()) return CG_ETIMEOUT;
         double rz;
         {
             double g[2];
-            grid_sum<BS, 2>(t.slot(SLOT_ITER), t.G, t.G, g, lds);
+            grid_sum<BS, 2>(t.slot(SLOT_ITER), t.G, g, lds);
             rz = g[0];
             rr = g[1];
         }
@@ -266,11 +267,11 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol
             {
                 double v[2] = {0.0, 0.0}, unused = 0.0;
                 step_r<LPR, BS, T>(s, rs, re, s.r, s.z, v[0], v[1], unused);
-                block_partials<BS, 2>(v, lds, t.slot(SLOT_CHECK), t.G, t.L);
+                block_partials<BS, 2>(v, lds, t.slot(SLOT_CHECK), t.L);
             }
             if (!t.sync()) return CG_ETIMEOUT;
             double g[2];
-            grid_sum<BS, 2>(t.slot(SLOT_CHECK), t.G, t.G, g, lds);
+            grid_sum<BS, 2>(t.slot(SLOT_CHECK), t.G, g, lds);
             if (sqrt(g[0]) <= thr) {
                 status = CG_CONVERGED;
                 rrt = g[0];
@@ -290,10 +291,10 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol
     if (rrt < 0.0) {  // report the true residual of the returned x
         double v[1] = {0.0}, unused0 = 0.0, unused1 = 0.0;
         step_r<LPR, BS, T>(s, rs, re, s.q, (T*)nullptr, v[0], unused0, unused1);
-        block_partials<BS, 1>(v, lds, t.slot(SLOT_CHECK), t.G, t.L);
+        block_partials<BS, 1>(v, lds, t.slot(SLOT_CHECK), t.L);
         if (!t.sync()) return CG_ETIMEOUT;
         double g[1];
-        grid_sum<BS, 1>(t.slot(SLOT_CHECK), t.G, t.G, g, lds);
+        grid_sum<BS, 1>(t.slot(SLOT_CHECK), t.G, g, lds);
         rrt = g[0];
     }
     if (writer) {

@@ -1,0 +1,166 @@
+// CSR-stream sparse products over "tiles" of whole rows.
+//
+// A tile is a run of consecutive rows whose nonzeros fit 64 * NPL slots (or a
+// single longer row).  One wave owns a tile at a time:
+//   1. each lane loads NPL (value, column) pairs at stride 64 -- every load is
+//      coalesced and all of them are independent, so a lane has 2 NPL loads
+//      plus NPL gathers in flight instead of a dependent chain per row;
+//   2. the products a_ij * x_j go to the wave's slice of LDS;
+//   3. one lane per row adds its row's products in stored column order.
+// Step 3 adds in the same order as a sequential CSR row sum and the products
+// are rounded on their own, so y = A x is bitwise the plain sequential result.
+// Rows longer than a tile take a vector path: the whole wave strides over the
+// row and reduces with a butterfly.
+//
+// Workgroups own equal, contiguous runs of tiles.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace jpcg {
+
+// A tile: rows [r0, r1) holding nonzeros [k0, k1).  Workgroup L owns tiles
+// [L * per_block, (L + 1) * per_block) -- an arithmetic map, so finding a
+// tile costs one 16-byte load and no index chase.
+struct TileMap {
+    const int4* tiles;
+    int T;
+    int per_block;
+};
+
+// Host: cut rows into tiles of at most `cap` nonzeros (a longer row forms a
+// tile of its own).
+inline void build_tiles(const std::vector<int>& rowptr, int cap, std::vector<int4>& tiles)
+{
+    const int n = (int)rowptr.size() - 1;
+    tiles.clear();
+    int r = 0;
+    while (r < n) {
+        const int k0 = rowptr[r];
+        int e = r + 1;
+        if (rowptr[e] - k0 <= cap) {
+            while (e < n && rowptr[e + 1] - k0 <= cap) ++e;
+        }
+        tiles.push_back(int4{r, e, k0, rowptr[e]});
+        r = e;
+    }
+}
+
+// Sum prod[a..b) in order; eight LDS reads are issued per batch.
+template <typename T>
+__device__ __forceinline__ T lds_row_sum(const T* prod, int a, int b)
+{
+    T s = T(0);
+    int k = a;
+    for (; k + 8 <= b; k += 8) {
+        T t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = prod[k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    for (; k < b; ++k) s += prod[k];
+    return s;
+}
+
+// Visit every row of the workgroup's tiles.
+//   gather(j)        raw operand(s) of column j (type GV), loaded per nonzero
+//   combine(v, g)    the product a_ij * (vector entry) from value v and g
+//   pre(i)           raw operand(s) of row i for the row step (type PV)
+//   row(i, sum, pv)  consumes a finished row; one lane per row
+//   prologue()       runs once per wave after the wave's first gathers are
+//                    issued (or at the end if the wave has no tile); it may
+//                    load and reduce scalars that combine/row depend on, so
+//                    that latency overlaps the gathers.  Returning false ends
+//                    the wave's work.
+// `prod` is this wave's LDS slice of 64 * NPL values.
+template <int NPL, typename T, typename Gather, typename Combine, typename Pre, typename Row, typename Prologue>
+__device__ __forceinline__ void tile_rows(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                          const T* __restrict__ val, const TileMap& tm, int L, T* prod,
+                                          Gather gather, Combine combine, Pre pre, Row row, Prologue prologue)
+{
+    constexpr int CAP = kWave * NPL;
+    using GV = decltype(gather(0));
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int nwaves = blockDim.x / kWave;
+    const int tb = L * tm.per_block;
+    const int t1 = min(tb + tm.per_block, tm.T);
+    bool ready = false;
+    for (int t = tb + wave; t < t1; t += nwaves) {
+        const int4 d = tm.tiles[t];
+        const int r0 = d.x, r1 = d.y, k0 = d.z, k1 = d.w;
+        if (k1 - k0 <= CAP) {
+            // Branch-free: every slot loads (slots past the tile read entry 0 and
+            // are zeroed), so all 2*NPL streaming loads issue before the first
+            // gather and all NPL gathers issue before the first product.
+            const int i0 = r0 + lane;
+            const bool has_row = i0 < r1;
+            const int ic = has_row ? i0 : r0;
+            const int ra = rowptr[ic], rb = rowptr[ic + 1];
+            const auto pv = pre(ic);
+            T v[NPL];
+            GV g[NPL];
+            int c[NPL];
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) {
+                const int k = k0 + lane + kWave * j;
+                const int kk = k < k1 ? k : 0;
+                v[j] = val[kk];
+                c[j] = col[kk];
+            }
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) {
+                const bool in = k0 + lane + kWave * j < k1;
+                c[j] = in ? c[j] : 0;
+                v[j] = in ? v[j] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) g[j] = gather(c[j]);
+            if (!ready) {
+                if (!prologue()) return;
+                ready = true;
+            }
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) prod[lane + kWave * j] = combine(v[j], g[j]);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (has_row) row(i0, lds_row_sum(prod, ra - k0, rb - k0), pv);
+            for (int i = i0 + kWave; i < r1; i += kWave)  // tiles of more than 64 rows
+                row(i, lds_row_sum(prod, rowptr[i] - k0, rowptr[i + 1] - k0), pre(i));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            // One row longer than a tile (r1 == r0 + 1).
+            if (!ready) {
+                if (!prologue()) return;
+                ready = true;
+            }
+            T acc = T(0);
+            for (int k = k0 + lane; k < k1; k += kWave) acc += combine(val[k], gather(col[k]));
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+            if (lane == 0) row(r0, acc, pre(r0));
+        }
+    }
+    if (!ready) prologue();
+}
+
+struct NoPre {
+    __device__ __forceinline__ int operator()(int) const { return 0; }
+};
+
+struct NoPrologue {
+    __device__ __forceinline__ bool operator()() const { return true; }
+};
+
+template <typename T>
+struct Mul {
+    __device__ __forceinline__ T operator()(T v, T g) const { return v * g; }
+};
+
+}  // namespace jpcg

@@ -56,31 +56,33 @@ def make_csr(a) -> tuple[capi.cg_csr, list]:
     return csr, keep
 
 
-def make_opts(precond="jacobi", fp32_copy=False, autotune=False, lanes_per_row=0, blocks_per_cu=0,
-              history=False) -> capi.cg_opts:
+def make_opts(precond="jacobi", fp32_copy=False, autotune=False, nnz_per_lane=0, blocks_per_cu=0,
+              history=False, block_size=0, chunk=0) -> capi.cg_opts:
     o = capi.cg_opts()
     capi.load().cg_opts_default(ctypes.byref(o))
     o.precond = {"jacobi": capi.CG_PRECOND_JACOBI, "none": capi.CG_PRECOND_NONE}[precond]
     o.fp32_copy = int(bool(fp32_copy))
     o.autotune = int(bool(autotune))
-    o.lanes_per_row = int(lanes_per_row)
+    o.nnz_per_lane = int(nnz_per_lane)
     o.blocks_per_cu = int(blocks_per_cu)
     o.history = int(bool(history))
+    o.block_size = int(block_size)
+    o.chunk = int(chunk)
     return o
 
 
 class Solver:
     """A cg_ctx: one SPD CSR matrix resident on the GPU."""
 
-    def __init__(self, a, precond="jacobi", fp32_copy=False, autotune=False, lanes_per_row=0,
-                 blocks_per_cu=0, history=False, stream=None):
+    def __init__(self, a, precond="jacobi", fp32_copy=False, autotune=False, nnz_per_lane=0,
+                 blocks_per_cu=0, history=False, block_size=0, chunk=0, stream=None):
         torch = _torch()
         self._lib = capi.load()
         self.n = int(a.n)
         self.nnz = int(a.rowptr[-1])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         csr, _keep = make_csr(a)
-        opts = make_opts(precond, fp32_copy, autotune, lanes_per_row, blocks_per_cu, history)
+        opts = make_opts(precond, fp32_copy, autotune, nnz_per_lane, blocks_per_cu, history, block_size, chunk)
         ctx = ctypes.c_void_p()
         rc = self._lib.cg_create(ctypes.byref(csr), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(ctx))
