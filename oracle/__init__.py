@@ -70,6 +70,8 @@ def lib():
         L.oracle_pcg.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, ctypes.POINTER(OracleInfo), P, P]
         L.oracle_pcg.restype = ctypes.c_int
+        L.oracle_pcg_sr.argtypes = L.oracle_pcg.argtypes
+        L.oracle_pcg_sr.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -120,8 +122,12 @@ def relres(a, b, x) -> float:
 
 
 def pcg(a, b, x0=None, tol: float = 1e-10, maxit: int = 0, precond: str = "jacobi",
-        sum_mode: int = 0, history: bool = False, trace: bool = False):
-    """Run the oracle solve.  Returns (x, info dict[, hist][, trace])."""
+        sum_mode: int = 0, history: bool = False, trace: bool = False, form: str = "standard"):
+    """Run the oracle solve.  Returns (x, info dict[, hist][, trace]).
+
+    form: "standard" (two reductions per iteration) or "single" (the
+    single-reduction Chronopoulos-Gear form of the same iteration).
+    """
     rowptr, col, val = _csr_arrays(a)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(a.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
@@ -130,8 +136,9 @@ def pcg(a, b, x0=None, tol: float = 1e-10, maxit: int = 0, precond: str = "jacob
     tr = np.full((mi + 1, 4, a.n), np.nan) if trace else None
     info = OracleInfo()
     pc = {"none": 0, "jacobi": 1}[precond]
-    lib().oracle_pcg(a.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), tol, mi, pc, sum_mode,
-                     ctypes.byref(info), _p(hist) if history else None, _p(tr) if trace else None)
+    fn = {"standard": lib().oracle_pcg, "single": lib().oracle_pcg_sr}[form]
+    fn(a.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), tol, mi, pc, sum_mode,
+       ctypes.byref(info), _p(hist) if history else None, _p(tr) if trace else None)
     d = info.as_dict()
     out = [x, d]
     if history:

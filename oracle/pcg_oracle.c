@@ -222,3 +222,122 @@ out:
     free(diag); free(r); free(z); free(p); free(q);
     return status;
 }
+
+/*
+ * The same solve in the single-reduction form of Chronopoulos and Gear
+ * (J. Comput. Appl. Math. 25, 1989): s = A p is carried by a recurrence and
+ * the product is applied to u = M^{-1} r, so r'u, w'u (w = A u) and r'r come
+ * from one reduction per iteration; p'Ap is recovered as
+ * sigma = delta - beta * gamma / alpha.  In exact arithmetic the iterates are
+ * those of oracle_pcg.  Stopping rules, statuses, history and trace follow
+ * oracle_pcg (trace slots hold x, r, u, p).
+ */
+int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
+                  const double *b, double *x, double tol, int maxit, int precond,
+                  int sum_mode, oracle_info *info, double *hist, double *trace)
+{
+    if (n <= 0 || !rowptr || !col || !val || !b || !x || !info || !(tol >= 0.0))
+        return ORC_EINVAL;
+    if (maxit <= 0) maxit = n;
+    memset(info, 0, sizeof(*info));
+
+    double *diag = malloc(sizeof(double) * (size_t)n);
+    double *r = malloc(sizeof(double) * (size_t)n);
+    double *u = malloc(sizeof(double) * (size_t)n);
+    double *w = malloc(sizeof(double) * (size_t)n);
+    double *p = malloc(sizeof(double) * (size_t)n);
+    double *sv = malloc(sizeof(double) * (size_t)n);
+    double *t = malloc(sizeof(double) * (size_t)n);
+    if (!diag || !r || !u || !w || !p || !sv || !t) {
+        free(diag); free(r); free(u); free(w); free(p); free(sv); free(t);
+        return ORC_ENOMEM;
+    }
+    int status = ORC_MAXIT;
+    for (int i = 0; i < n; ++i) {
+        diag[i] = 1.0;
+        if (precond == 1) {
+            double d = 0.0;
+            int found = 0;
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                if (col[k] == i) { d += val[k]; found = 1; }
+            if (!found || !(d > 0.0)) { status = ORC_EDIAG; goto out; }
+            diag[i] = d;
+        }
+    }
+
+    double nb = sqrt(oracle_dot(n, b, b, sum_mode));
+    if (nb == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        if (hist) hist[0] = 0.0;
+        status = ORC_CONVERGED;
+        goto out;
+    }
+    double thr = tol * nb;
+    oracle_spmv(n, rowptr, col, val, x, r);
+    for (int i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    double rn = sqrt(oracle_dot(n, r, r, sum_mode));
+    if (hist) hist[0] = rn / nb;
+    info->relres_recur = rn / nb;
+    if (rn <= thr) {
+        info->relres_true = rn / nb;
+        snapshot(trace, n, 0, x, r, NULL, NULL);
+        status = ORC_CONVERGED;
+        goto out;
+    }
+    /* u0 = M^{-1} r0, w0 = A u0, p0 = u0, s0 = w0 */
+    for (int i = 0; i < n; ++i) u[i] = r[i] / diag[i];
+    oracle_spmv(n, rowptr, col, val, u, w);
+    double gamma = oracle_dot(n, r, u, sum_mode);
+    double sigma = oracle_dot(n, w, u, sum_mode);   /* delta_0 = p0' A p0 */
+    memcpy(p, u, sizeof(double) * (size_t)n);
+    memcpy(sv, w, sizeof(double) * (size_t)n);
+    snapshot(trace, n, 0, x, r, u, p);
+
+    int k = 0;
+    while (k < maxit) {
+        if (!(sigma > 0.0) || !isfinite(sigma)) { status = ORC_BREAKDOWN; break; }
+        double alpha = gamma / sigma;
+        for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * sv[i];
+        ++k;
+        rn = sqrt(oracle_dot(n, r, r, sum_mode));
+        if (hist) hist[k] = rn / nb;
+        info->relres_recur = rn / nb;
+        if (rn <= thr) {                                    /* continue-condition */
+            oracle_spmv(n, rowptr, col, val, x, t);
+            for (int i = 0; i < n; ++i) t[i] = b[i] - t[i];
+            double tn = sqrt(oracle_dot(n, t, t, sum_mode));
+            if (tn <= thr) {
+                snapshot(trace, n, k, x, r, NULL, NULL);
+                status = ORC_CONVERGED;
+                break;
+            }
+            memcpy(r, t, sizeof(double) * (size_t)n);       /* residual replacement */
+            info->replacements += 1;
+        }
+        for (int i = 0; i < n; ++i) u[i] = r[i] / diag[i];
+        oracle_spmv(n, rowptr, col, val, u, w);
+        double gamma_new = oracle_dot(n, r, u, sum_mode);
+        double delta = oracle_dot(n, w, u, sum_mode);
+        if (!(gamma_new > 0.0) || !isfinite(gamma_new)) {
+            snapshot(trace, n, k, x, r, u, NULL);
+            status = ORC_BREAKDOWN;
+            break;
+        }
+        double beta = gamma_new / gamma;
+        sigma = delta - beta * gamma_new / alpha;
+        gamma = gamma_new;
+        for (int i = 0; i < n; ++i) p[i] = u[i] + beta * p[i];
+        for (int i = 0; i < n; ++i) sv[i] = w[i] + beta * sv[i];
+        snapshot(trace, n, k, x, r, u, p);
+    }
+    info->iters = k;
+    oracle_spmv(n, rowptr, col, val, x, t);
+    for (int i = 0; i < n; ++i) t[i] = b[i] - t[i];
+    info->relres_true = sqrt(oracle_dot(n, t, t, sum_mode)) / nb;
+
+out:
+    info->status = status;
+    free(diag); free(r); free(u); free(w); free(p); free(sv); free(t);
+    return status;
+}

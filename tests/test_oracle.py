@@ -45,12 +45,16 @@ def test_spmv_brute_force():
     assert np.all(np.abs(y - ref) <= bound)
 
 
+FORMS = ["standard", "single"]
+
+
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("n,seed,pc", [(4, 0, "jacobi"), (6, 1, "jacobi"), (7, 2, "none"), (8, 3, "jacobi")])
-def test_cg_matches_cholesky(n, seed, pc):
+def test_cg_matches_cholesky(n, seed, pc, form):
     a, b = W.problem(n, seed)
     d = a.to_dense()
     xc = sla.cho_solve(sla.cho_factor(d), b)
-    x, info = oracle.pcg(a, b, tol=1e-10, precond=pc)
+    x, info = oracle.pcg(a, b, tol=1e-10, precond=pc, form=form)
     assert info["status"] == oracle.CONVERGED
     assert info["relres_true"] <= 1e-10
     kappa = np.linalg.cond(d)
@@ -61,25 +65,27 @@ def test_cg_matches_cholesky(n, seed, pc):
     assert err <= 1e-6
 
 
-def test_cg_well_conditioned_to_roundoff():
+@pytest.mark.parametrize("form", FORMS)
+def test_cg_well_conditioned_to_roundoff(form):
     rng = np.random.default_rng(4)
     n = 40
     g = rng.standard_normal((n, n))
     d = g @ g.T / n + 3 * np.eye(n)
     b = rng.standard_normal(n)
-    x, info = oracle.pcg(dense_csr(d), b, tol=1e-14, precond="jacobi")
+    x, info = oracle.pcg(dense_csr(d), b, tol=1e-14, precond="jacobi", form=form)
     xc = sla.cho_solve(sla.cho_factor(d), b)
     assert info["status"] == oracle.CONVERGED and info["iters"] <= n
     assert np.linalg.norm(x - xc) / np.linalg.norm(xc) <= 1e-12
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("pc", ["jacobi", "none"])
-def test_invariants(pc):
+def test_invariants(pc, form):
     # Orthogonality r_i' z_j = 0, conjugacy p_i' A p_j = 0, monotone A-norm error, Chebyshev bound.
     a, b = W.problem(5, 7)
     d = a.to_dense()
     xs = sla.cho_solve(sla.cho_factor(d), b)
-    x, info, tr = oracle.pcg(a, b, tol=1e-10, precond=pc, trace=True)
+    x, info, tr = oracle.pcg(a, b, tol=1e-10, precond=pc, trace=True, form=form)
     k = info["iters"]
     assert info["status"] == oracle.CONVERGED and k >= 10
     X, R, Z, P = tr[:, 0], tr[:, 1], tr[:, 2], tr[:, 3]
@@ -105,20 +111,21 @@ def test_invariants(pc):
     assert np.all(anorm <= 2 * rate ** ks * anorm[0] * (1 + 1e-9) + 1e-14 * anorm[0])
 
 
-def test_distinct_eigenvalues_finite_termination():
+@pytest.mark.parametrize("form", FORMS)
+def test_distinct_eigenvalues_finite_termination(form):
     rng = np.random.default_rng(1)
     n = 30
     u = rng.standard_normal(n)
     d = np.eye(n) + np.outer(u, u)  # eigenvalues {1, 1 + |u|^2}
-    x, info = oracle.pcg(dense_csr(d), rng.standard_normal(n), tol=1e-12, precond="none")
+    x, info = oracle.pcg(dense_csr(d), rng.standard_normal(n), tol=1e-12, precond="none", form=form)
     assert info["status"] == oracle.CONVERGED and info["iters"] == 2
     d3 = np.diag(np.repeat([1.0, 4.0, 9.0], 10))
-    x, info = oracle.pcg(dense_csr(d3), rng.standard_normal(n), tol=1e-12, precond="none")
+    x, info = oracle.pcg(dense_csr(d3), rng.standard_normal(n), tol=1e-12, precond="none", form=form)
     assert info["iters"] == 3
     # A diagonal matrix under Jacobi is the identity after preconditioning: one step.
     dd = np.diag(rng.uniform(1, 100, n))
     b = rng.standard_normal(n)
-    x, info = oracle.pcg(dense_csr(dd), b, tol=1e-14, precond="jacobi")
+    x, info = oracle.pcg(dense_csr(dd), b, tol=1e-14, precond="jacobi", form=form)
     assert info["iters"] == 1 and np.allclose(x, b / np.diag(dd), rtol=1e-15)
 
 
@@ -128,26 +135,27 @@ def test_termination_within_n():
     assert info["status"] == oracle.CONVERGED and info["iters"] <= a.n
 
 
-def test_degenerate_cases():
+@pytest.mark.parametrize("form", FORMS)
+def test_degenerate_cases(form):
     a, b = W.problem(5, 3)
-    x, info = oracle.pcg(a, np.zeros(a.n), x0=np.ones(a.n))
+    x, info = oracle.pcg(a, np.zeros(a.n), x0=np.ones(a.n), form=form)
     assert info["status"] == oracle.CONVERGED and info["iters"] == 0 and not x.any()
     xs = sla.cho_solve(sla.cho_factor(a.to_dense()), b)
-    x, info = oracle.pcg(a, b, x0=xs)
+    x, info = oracle.pcg(a, b, x0=xs, form=form)
     assert info["status"] == oracle.CONVERGED and info["iters"] == 0
-    x, info = oracle.pcg(a, b, maxit=1)
+    x, info = oracle.pcg(a, b, maxit=1, form=form)
     assert info["status"] == oracle.MAXIT and info["iters"] == 1
     bn = b.copy()
     bn[3] = np.nan
-    x, info = oracle.pcg(a, bn)
+    x, info = oracle.pcg(a, bn, form=form)
     assert info["status"] == oracle.BREAKDOWN
     # Indefinite: flip one diagonal block sign.
     ind = dense_csr(np.diag([1.0, 2.0, -3.0, 4.0]))
-    x, info = oracle.pcg(ind, np.ones(4), precond="none")
+    x, info = oracle.pcg(ind, np.ones(4), precond="none", form=form)
     assert info["status"] == oracle.BREAKDOWN
     # Jacobi needs a positive diagonal.
     bad = dense_csr(np.array([[0.0, 1.0], [1.0, 2.0]]))
-    x, info = oracle.pcg(bad, np.ones(2), precond="jacobi")
+    x, info = oracle.pcg(bad, np.ones(2), precond="jacobi", form=form)
     assert info["status"] == oracle.EDIAG
 
 
@@ -173,3 +181,20 @@ def test_self_consistency_pairwise_16():
     assert np.linalg.norm(x0 - x1) / np.linalg.norm(x0) <= 1e-8
     xm0, xm1 = x0 - x0.mean(), x1 - x1.mean()
     assert np.linalg.norm(xm0 - xm1) / np.linalg.norm(xm0) <= 1e-6
+
+
+def test_single_reduction_form_tracks_standard_iterates():
+    # Same Krylov iterates in exact arithmetic: early iterates agree to rounding level,
+    # and on the FEM system the counts agree within +-2 and the solutions within 1e-8.
+    a, b = W.problem(6, 4)
+    _, i0, t0 = oracle.pcg(a, b, trace=True)
+    _, i1, t1 = oracle.pcg(a, b, trace=True, form="single")
+    for k in range(10):
+        for slot in (0, 1, 3):  # x, r, p
+            ref = np.linalg.norm(t0[k, slot])
+            assert np.linalg.norm(t1[k, slot] - t0[k, slot]) <= 1e-9 * ref, (k, slot)
+    a, b = W.problem(16, 0)
+    x0, i0 = oracle.pcg(a, b)
+    x1, i1 = oracle.pcg(a, b, form="single")
+    assert abs(i0["iters"] - i1["iters"]) <= 2 and i1["relres_true"] <= 1e-10
+    assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) <= 1e-8

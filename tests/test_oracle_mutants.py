@@ -30,10 +30,19 @@ MUTANTS = {
     "norm_without_sqrt": ("rn = sqrt(oracle_dot(n, r, r, sum_mode));\n        if (hist)",
                           "rn = (oracle_dot(n, r, r, sum_mode));\n        if (hist)"),
     "p_dot_wrong_operand": ("sigma = oracle_dot(n, p, q, sum_mode)", "sigma = oracle_dot(n, q, q, sum_mode)"),
+    # the single-reduction form
+    "sr_sigma_sign": ("sigma = delta - beta * gamma_new / alpha", "sigma = delta + beta * gamma_new / alpha"),
+    "sr_s_drops_beta": ("sv[i] = w[i] + beta * sv[i]", "sv[i] = w[i]"),
+    "sr_residual_uses_w": ("r[i] = r[i] - alpha * sv[i]", "r[i] = r[i] - alpha * w[i]"),
+    "sr_product_of_r": ("oracle_spmv(n, rowptr, col, val, u, w);\n        double gamma_new",
+                        "oracle_spmv(n, rowptr, col, val, r, w);\n        double gamma_new"),
+    "sr_gamma_stale": ("        gamma = gamma_new;\n", "        gamma = gamma;\n"),
 }
 
+SINGLE_FORM = {k for k in MUTANTS if k.startswith("sr_")}
 
-def _pins_pass() -> bool:
+
+def _pins_pass(form: str = "standard") -> bool:
     """A compact subset of the oracle pins; True when every one holds."""
     try:
         rng = np.random.default_rng(0)
@@ -43,12 +52,12 @@ def _pins_pass() -> bool:
         if np.max(np.abs(oracle.spmv(a, x) - d @ x)) > 1e-12:
             return False
         xc = sla.cho_solve(sla.cho_factor(d), b)
-        xs, info = oracle.pcg(a, b, tol=1e-10)
+        xs, info = oracle.pcg(a, b, tol=1e-10, form=form)
         if info["status"] != oracle.CONVERGED or np.linalg.norm(xs - xc) > 1e-6 * np.linalg.norm(xc):
             return False
         if np.linalg.norm(b - d @ xs) > 1e-10 * np.linalg.norm(b) * 1.0001:
             return False
-        xs, info, hist, tr = oracle.pcg(a, b, tol=1e-10, history=True, trace=True)
+        xs, info, hist, tr = oracle.pcg(a, b, tol=1e-10, history=True, trace=True, form=form)
         nb = np.linalg.norm(b)
         for k in range(6):
             if abs(hist[k] - np.linalg.norm(b - d @ tr[k, 0]) / nb) > 1e-10 * hist[0]:
@@ -63,7 +72,7 @@ def _pins_pass() -> bool:
         x, info = oracle.pcg(
             W.CSR(n, np.arange(0, n * n + 1, n, dtype=np.int32), np.tile(np.arange(n, dtype=np.int32), n),
                   (np.eye(n) + np.outer(u, u)).ravel()),
-            rng.standard_normal(n), tol=1e-12, precond="none")
+            rng.standard_normal(n), tol=1e-12, precond="none", form=form)
         return info["status"] == oracle.CONVERGED and info["iters"] == 2
     except Exception:
         return False
@@ -99,7 +108,7 @@ def test_unmutated_copy_passes(swap_lib):
         src = f.read()
     with tempfile.TemporaryDirectory() as tmp:
         _load_variant(src, tmp)
-        assert _pins_pass()
+        assert _pins_pass("standard") and _pins_pass("single")
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -107,7 +116,12 @@ def test_mutant_is_caught(name, swap_lib):
     with open(oracle.SRC) as f:
         src = f.read()
     old, new = MUTANTS[name]
-    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    # Sites shared by both forms are mutated at their first occurrence, which is
+    # in the standard form -- the form whose pins are then run.
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    if name in SINGLE_FORM:
+        assert src.count(old) == 1, f"mutation site for {name} not unique"
     with tempfile.TemporaryDirectory() as tmp:
-        _load_variant(src.replace(old, new), tmp)
-        assert not _pins_pass(), f"pins did not catch {name}"
+        _load_variant(src.replace(old, new, 1), tmp)
+        form = "single" if name in SINGLE_FORM else "standard"
+        assert not _pins_pass(form), f"pins did not catch {name}"
