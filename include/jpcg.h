@@ -53,6 +53,12 @@ enum { CG_MEM_HOST = 0, CG_MEM_DEVICE = 1 };
 /* Preconditioner choice; 0 in cg_opts.precond selects the default (Jacobi). */
 enum { CG_PRECOND_DEFAULT = 0, CG_PRECOND_JACOBI = 1, CG_PRECOND_NONE = 2 };
 
+/* Form of the iteration.  Both compute the same Krylov iterates in exact
+ * arithmetic and stop by the same rules; the single-reduction form
+ * (Chronopoulos and Gear) carries s = A p by a recurrence so that each
+ * iteration needs one product, one reduction and one kernel. */
+enum { CG_FORM_STANDARD = 0, CG_FORM_SINGLE_REDUCTION = 1 };
+
 /* A square CSR matrix (see the conventions above). */
 typedef struct {
     int32_t n;
@@ -73,7 +79,8 @@ typedef struct {
     int32_t history;       /* 1: record ||r_k|| / ||b|| for every iteration            */
     int32_t block_size;    /* 0 = default; else 256, 512 or 1024 threads per workgroup  */
     int32_t chunk;         /* 0 = default; CG iterations per launched hipGraph chunk    */
-    int32_t reserved[8];
+    int32_t form;          /* CG_FORM_STANDARD (default) or CG_FORM_SINGLE_REDUCTION    */
+    int32_t reserved[7];
 } cg_opts;
 
 /* Result of a solve. */
@@ -94,7 +101,7 @@ typedef struct {
     int32_t grid;          /* workgroups of every solver kernel and of spmv       */
     int32_t tiles;         /* product tiles (runs of whole rows) of the matrix    */
     int32_t chunk;         /* iterations per hipGraph chunk                       */
-    int32_t pad;
+    int32_t form;          /* CG_FORM_STANDARD or CG_FORM_SINGLE_REDUCTION        */
     double spmv_us;        /* autotuner's best spmv time, 0 if not tuned          */
     double iter_us;        /* autotuner's best solver time per iteration, or 0    */
 } cg_config;
@@ -132,9 +139,46 @@ int cg_create(const cg_csr *A, const cg_opts *opts, void *hip_stream, cg_ctx **o
  */
 int cg_solve(cg_ctx *ctx, const double *b, double *x, double tol, int32_t maxit, cg_info *info);
 
+/*
+ * Mixed-precision solve (FP32 inner Jacobi-PCG, FP64 refinement): repeat
+ *   r = b - A x in FP64;  stop if ||r|| <= tol ||b|| (FP64 test);
+ *   solve A d = r / ||r|| with FP32 Jacobi-PCG on the FP32 copy of A (FP64
+ *     dot products) from d = 0 until its recurrence residual is <= tol_inner;
+ *   x += ||r|| d in FP64,
+ * at most maxit_outer times (<= 0: 50); each inner solve runs at most
+ * maxit_inner iterations (<= 0: n); tol_inner = 0 means 1e-5.  Requires a
+ * context created with fp32_copy = 1, else CG_EINVAL.  b, x as in cg_solve.
+ * info->iters counts inner iterations, info->outer refinement steps, and
+ * info->relres_true is the FP64 ||b - A x|| / ||b|| of the returned x.
+ * Returns CG_CONVERGED, CG_MAXIT (outer limit), CG_BREAKDOWN (non-finite
+ * residual) or an API error.
+ */
+int cg_solve_mixed(cg_ctx *ctx, const double *b, double *x, double tol, int32_t maxit_outer,
+                   double tol_inner, int32_t maxit_inner, cg_info *info);
+
 /* y = A x (the paper's "DGEMV(sparse)").  Device pointers to float64[n], x != y.
  * Asynchronous on the context's stream.  Returns 0 or an API error. */
 int spmv(cg_ctx *ctx, const double *x, double *y);
+
+/*
+ * Y = A X for a row-major n x s block (1 <= s <= 64), device pointers,
+ * X != Y.  Column j of Y is the sequential CSR product of column j of X (each
+ * row summed in stored order).  Asynchronous on the context's stream.
+ */
+int spmm(cg_ctx *ctx, const double *X, double *Y, int32_t s);
+
+/*
+ * Solve A X = B for s right-hand sides (1 <= s <= 64; row-major n x s device
+ * blocks; X holds X0 on entry).  Each column runs its own Jacobi-PCG
+ * recurrence with cg_solve's stopping rules (continue-condition, true-
+ * residual confirmation, replacement); the columns share one sparse product,
+ * one update and the scalar steps per iteration.  info, if not NULL, points
+ * to s cg_info records (one per column; seconds is the whole call).  Returns
+ * CG_CONVERGED if every column converged, else the largest column status
+ * (CG_MAXIT, CG_BREAKDOWN), or an API error.  Synchronises the stream.
+ */
+int cg_solve_multi(cg_ctx *ctx, const double *B, double *X, int32_t s, double tol, int32_t maxit,
+                   cg_info *info);
 
 /* Copy up to `cap` entries of the last solve's residual history
  * (||r_k|| / ||b||, k = 0..iters) into host memory; returns the count

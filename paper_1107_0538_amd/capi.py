@@ -17,6 +17,8 @@ CG_CONVERGED, CG_MAXIT, CG_BREAKDOWN = 0, 1, 2
 CG_EINVAL, CG_EDIAG, CG_ENOMEM, CG_EHIP, CG_ETIMEOUT, CG_EUNSUPPORTED = -1, -2, -3, -4, -5, -6
 CG_MEM_HOST, CG_MEM_DEVICE = 0, 1
 CG_PRECOND_DEFAULT, CG_PRECOND_JACOBI, CG_PRECOND_NONE = 0, 1, 2
+CG_FORM_STANDARD, CG_FORM_SINGLE_REDUCTION = 0, 1
+FORMS = {"standard": CG_FORM_STANDARD, "single": CG_FORM_SINGLE_REDUCTION}
 
 _P = ctypes.c_void_p
 
@@ -30,7 +32,7 @@ class cg_opts(ctypes.Structure):
     _fields_ = [("precond", ctypes.c_int32), ("fp32_copy", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("nnz_per_lane", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("history", ctypes.c_int32), ("block_size", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class cg_info(ctypes.Structure):
@@ -44,7 +46,7 @@ class cg_info(ctypes.Structure):
 
 class cg_config(ctypes.Structure):
     _fields_ = [("nnz_per_lane", ctypes.c_int32), ("block_size", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("tiles", ctypes.c_int32), ("chunk", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("tiles", ctypes.c_int32), ("chunk", ctypes.c_int32), ("form", ctypes.c_int32),
                 ("spmv_us", ctypes.c_double), ("iter_us", ctypes.c_double)]
 
     def as_dict(self):
@@ -56,7 +58,12 @@ SIGNATURES = {
     "cg_opts_default": (None, [ctypes.POINTER(cg_opts)]),
     "cg_create": (ctypes.c_int, [ctypes.POINTER(cg_csr), ctypes.POINTER(cg_opts), _P, ctypes.POINTER(_P)]),
     "cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(cg_info)]),
+    "cg_solve_mixed": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_int32, ctypes.POINTER(cg_info)]),
     "spmv": (ctypes.c_int, [_P, _P, _P]),
+    "spmm": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "cg_solve_multi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.POINTER(cg_info)]),
     "cg_get_history": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "cg_get_config": (ctypes.c_int, [_P, ctypes.POINTER(cg_config)]),
     "cg_destroy": (None, [_P]),

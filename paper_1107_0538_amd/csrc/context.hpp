@@ -21,17 +21,22 @@ struct cg_ctx {
     double* dinv = nullptr;
     float* val32 = nullptr;   // fp32_copy
     float* dinv32 = nullptr;  // fp32_copy
+    float* rowsum32 = nullptr;  // fp32_copy: row sums of A (FP64 sums, FP32 storage)
     std::vector<int> h_rowptr;
 
-    // Work vectors for single-RHS solves (n each).
-    double* r = nullptr;
-    double* z = nullptr;
-    double* p0 = nullptr;
-    double* p1 = nullptr;
-    double* q = nullptr;
+    // Work vectors for single-RHS solves (n each, one allocation): the
+    // standard form uses r, z, p (two), q; the single-reduction form uses
+    // r, w, s (two each) and p.
+    static constexpr int kWorkVecs = 7;
+    double* work[kWorkVecs] = {};
 
     // Graph-chunked solver for the chosen launch shape.
-    struct cg_graphs* graphs = nullptr;
+    struct cg_graphs* graphs = nullptr;      // the context's form, FP64
+    struct cg_graphs* graphs_std = nullptr;  // standard form FP64 (mixed-form outer residual)
+    struct cg_graphs* graphs32 = nullptr;    // standard form FP32 (mixed-form inner solve)
+    void* mixed_dev = nullptr;
+    void* mixed_host = nullptr;
+    struct cg_multi* multi = nullptr;        // multi-RHS solver for one block width
     double* hist = nullptr;
     int hist_cap = 0;
     int hist_len = 0;
@@ -41,6 +46,7 @@ struct cg_ctx {
     long long limit_ticks = 0;
 
     // Launch shape.
+    int form = CG_FORM_STANDARD;
     int npl = 8;   // nonzeros per lane of a product tile
     int bs = 512;
     int grid = 0;
@@ -57,5 +63,8 @@ namespace jpcg {
 void partition_rows(const std::vector<int>& rowptr, int G, std::vector<int>& out);
 
 int set_error(cg_ctx* c, int code, const std::string& msg);
+
+// Free the multi-RHS solver state of a context (multi.hip).
+void free_multi(cg_ctx* c);
 
 }  // namespace jpcg

@@ -1,0 +1,619 @@
+// Multi-RHS Jacobi-PCG: s <= 64 independent CG recurrences (one per column of
+// a row-major N x s block) sharing one sparse product per iteration.
+//
+// Each column follows the FP64 oracle's loop exactly; the columns only share
+// launches.  Layout: lane j of a wave owns column j, so a gathered row of X is
+// one coalesced s * 8-byte load and a CSR value/index is a wave-uniform
+// (scalar) load.  Every column's row sum runs in stored order with separate
+// multiply and add, so spmm's column j equals the sequential CSR product.
+//
+// Per iteration (parity P), all captured in hipGraph chunks:
+//   k_mr_direction  p_j = z_j + beta_j p_j (on the fly), q = A p, partials of p_j'q_j
+//   k_mr_scalars    one workgroup: sigma_j, alpha_j, breakdown per column
+//   k_mr_update     x += alpha p, r -= alpha q, z = M^-1 r, partials of r'z, r'r
+//   k_mr_scalars    one workgroup: continue-condition, breakdown, limit, beta
+// A column whose recurrence residual passes is frozen (its p is carried
+// forward unchanged) and waits; when no column is active the host runs one
+// true-residual check for all waiting columns, exactly the oracle's check,
+// and resumes replaced ones.  Reductions of per-workgroup partials run in a
+// separate one-workgroup kernel: a redundant per-wave reduction of 64 columns
+// would multiply cache traffic by the grid size.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "context.hpp"
+
+namespace jpcg {
+
+enum ColStatus : int {
+    COL_ACTIVE = 0,
+    COL_PENDING = 1,  // recurrence residual passed; true residual not yet checked
+    COL_CONVERGED = 2,
+    COL_MAXIT = 3,
+    COL_BREAKDOWN = 4,
+    COL_ZERO = 5,     // b_j = 0
+    COL_UNUSED = 6,   // lane >= s
+};
+
+constexpr int kCols = 64;
+
+struct MrState {
+    int stop;          // no column active
+    int any_pending;
+    int pad[2];
+    int status[kCols];
+    int iters[kCols];
+    int repl[kCols];
+    int first[kCols];  // next direction step is the first for this column (p = z)
+    double rho[kCols];
+    double alpha[kCols];
+    double beta[kCols];
+    double nb[kCols];
+    double thr[kCols];
+    double rr[kCols];
+    double rr_true[kCols];
+};
+
+template <typename T>
+struct MrArgs {
+    int n, s;
+    const int* __restrict__ rowptr;
+    const int* __restrict__ col;
+    const T* __restrict__ val;
+    const T* __restrict__ dinv;
+    const T* B;
+    T* X;
+    T* R;
+    T* Z;
+    T* P[2];
+    T* Q;
+    int G;
+    int rows_per_block;
+    double* part;  // [G][3][64]
+    MrState* st;
+    int maxit;
+    double tol;
+};
+
+__device__ __forceinline__ int mr_logical(int G) { return xcd_logical_block((int)blockIdx.x, G); }
+
+// Block-reduce K per-lane quantities over the waves (lane = column) and write
+// them to part[L][k][lane].
+template <int BS, int K>
+__device__ __forceinline__ void mr_block_partials(double (&v)[K], double* part, int L)
+{
+    constexpr int NW = BS / kWave;
+    __shared__ double lds[NW][K][kWave];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[w][k][lane] = v[k];
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int j = 0; j < NW; ++j) t += lds[j][k][lane];
+            part[((size_t)L * K + k) * kWave + lane] = t;
+        }
+    }
+}
+
+// One wave: y_lane = sum_k a_ik x[col_k][lane] for row i in stored order,
+// without contraction, so each column is the sequential CSR row sum.
+template <typename T, typename Gather>
+__device__ __forceinline__ T mr_row(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                    const T* __restrict__ val, int i, Gather gather)
+{
+#pragma clang fp contract(off)
+    const int k0 = rowptr[i], k1 = rowptr[i + 1];
+    T acc = T(0);
+    int k = k0;
+    for (; k + 8 <= k1; k += 8) {
+        T v[8], g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            v[u] = val[k + u];
+            g[u] = gather(col[k + u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = acc + v[u] * g[u];
+    }
+    for (; k < k1; ++k) acc = acc + val[k] * gather(col[k]);
+    return acc;
+}
+
+// Residual R = B - A X with Z = M^-1 R and partials (r'r, r'z, b'b) per column.
+// mode 0: setup (every column; clears both P buffers), 1: check (only pending
+// columns are rewritten), 2: report (nothing is written but the partials).
+template <int BS, typename T>
+__global__ __launch_bounds__(BS) void k_mr_residual(MrArgs<T> a, int mode)
+{
+    const int L = mr_logical(a.G);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int rs = min(L * a.rows_per_block, a.n), re = min(rs + a.rows_per_block, a.n);
+    const int s = a.s;
+    const bool used = lane < s;
+    const int cl = used ? lane : 0;
+    const bool write = used && (mode == 0 || (mode == 1 && a.st->status[lane] == COL_PENDING));
+    double v[3] = {0.0, 0.0, 0.0};
+    const T* __restrict__ X = a.X;
+    for (int i = rs + w; i < re; i += BS / kWave) {
+        const T ax = mr_row<T>(a.rowptr, a.col, a.val, i, [&](int j) { return X[(size_t)j * s + cl]; });
+        const size_t o = (size_t)i * s + cl;
+        const T bi = a.B[o];
+        const T ri = bi - ax;
+        const T zi = a.dinv[i] * ri;
+        if (write) {
+            a.R[o] = ri;
+            a.Z[o] = zi;
+        }
+        if (mode == 0 && used) {
+            a.P[0][o] = T(0);
+            a.P[1][o] = T(0);
+        }
+        if (used) {
+            v[0] += (double)ri * (double)ri;
+            v[1] += (double)ri * (double)zi;
+            v[2] += (double)bi * (double)bi;
+        }
+    }
+    mr_block_partials<BS, 3>(v, a.part, L);
+}
+
+// q = A p_new with p_new = z + beta p_old (active), z (first step) or p_old
+// (frozen: carried forward); partials of p_new'q.
+template <int BS, typename T>
+__global__ __launch_bounds__(BS) void k_mr_direction(MrArgs<T> a, int P)
+{
+    const MrState* st = a.st;
+    if (st->stop) return;
+    const int L = mr_logical(a.G);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int rs = min(L * a.rows_per_block, a.n), re = min(rs + a.rows_per_block, a.n);
+    const int s = a.s;
+    const bool used = lane < s;
+    const int cl = used ? lane : 0;
+    const int status = used ? st->status[lane] : COL_UNUSED;
+    const bool active = status == COL_ACTIVE;
+    const bool first = active && st->first[lane];
+    const T beta = (T)st->beta[lane];
+    const T* __restrict__ Z = a.Z;
+    const T* __restrict__ pold = a.P[P ^ 1];
+    T* __restrict__ pnew = a.P[P];
+    auto pval = [&](size_t o) -> T {
+        const T po = pold[o];
+        return active ? (first ? Z[o] : fma_t(beta, po, Z[o])) : po;
+    };
+    double v[1] = {0.0};
+    for (int i = rs + w; i < re; i += BS / kWave) {
+        const T qi = mr_row<T>(a.rowptr, a.col, a.val, i, [&](int j) { return pval((size_t)j * s + cl); });
+        const size_t o = (size_t)i * s + cl;
+        const T pi = pval(o);
+        if (used) {
+            pnew[o] = pi;
+            a.Q[o] = qi;
+            if (active) v[0] += (double)pi * (double)qi;
+        }
+    }
+    mr_block_partials<BS, 1>(v, a.part, L);
+}
+
+// x += alpha p, r -= alpha q, z = M^-1 r for active columns; partials of r'z, r'r.
+template <int BS, typename T>
+__global__ __launch_bounds__(BS) void k_mr_update(MrArgs<T> a, int P)
+{
+    const MrState* st = a.st;
+    if (st->stop) return;
+    const int L = mr_logical(a.G);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int rs = min(L * a.rows_per_block, a.n), re = min(rs + a.rows_per_block, a.n);
+    const int s = a.s;
+    const bool active = lane < s && st->status[lane] == COL_ACTIVE;
+    const T alpha = (T)st->alpha[lane < s ? lane : 0];
+    const T* __restrict__ p = a.P[P];
+    double v[2] = {0.0, 0.0};
+    if (active) {
+        for (int i = rs + w; i < re; i += BS / kWave) {
+            const size_t o = (size_t)i * s + lane;
+            a.X[o] = fma_t(alpha, p[o], a.X[o]);
+            const T ri = fma_t(-alpha, a.Q[o], a.R[o]);
+            a.R[o] = ri;
+            const T zi = a.dinv[i] * ri;
+            a.Z[o] = zi;
+            v[0] += (double)ri * (double)zi;
+            v[1] += (double)ri * (double)ri;
+        }
+    }
+    mr_block_partials<BS, 2>(v, a.part, L);
+}
+
+// One workgroup of 64 * NW threads reduces the G partials of K quantities per
+// column: wave w takes workgroups w, w + NW, ...; then waves combine in order.
+template <int NW, int K>
+__device__ __forceinline__ void mr_reduce(const double* part, int G, double (&out)[K])
+{
+    __shared__ double lds[NW][K][kWave];
+    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int g = w; g < G; g += NW) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += part[((size_t)g * K + k) * kWave + lane];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[w][k][lane] = acc[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) t += lds[j][k][lane];
+        out[k] = t;
+    }
+}
+
+enum MrPhase : int { MR_SETUP = 0, MR_SIGMA = 1, MR_ITER = 2, MR_CHECK = 3, MR_REPORT = 4 };
+
+// The per-column scalar steps, one workgroup of 4 waves; wave 0 lane j owns
+// column j's state.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mr_scalars(MrArgs<T> a, int phase)
+{
+    MrState* st = a.st;
+    if ((phase == MR_SIGMA || phase == MR_ITER) && st->stop) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    double g[3];
+    if (phase == MR_SIGMA) {
+        double t[1];
+        mr_reduce<4, 1>(a.part, a.G, t);
+        g[0] = t[0];
+    } else if (phase == MR_ITER) {
+        double t[2];
+        mr_reduce<4, 2>(a.part, a.G, t);
+        g[0] = t[0];
+        g[1] = t[1];
+    } else {
+        mr_reduce<4, 3>(a.part, a.G, g);
+    }
+    if (threadIdx.x >= kWave) return;
+    const int j = lane;
+    int status = j < a.s ? st->status[j] : COL_UNUSED;
+    if (phase == MR_SETUP) {
+        // g = (r'r, r'z, b'b) of r0
+        st->repl[j] = 0;
+        st->iters[j] = 0;
+        st->first[j] = 1;
+        st->beta[j] = 0.0;
+        st->alpha[j] = 0.0;
+        if (j >= a.s) {
+            status = COL_UNUSED;
+        } else {
+            const double nb = sqrt(g[2]);
+            st->nb[j] = nb;
+            st->thr[j] = a.tol * nb;
+            st->rr[j] = g[0];
+            st->rho[j] = g[1];
+            st->rr_true[j] = -1.0;
+            if (nb == 0.0) {
+                status = COL_ZERO;
+                st->rr_true[j] = 0.0;
+            } else if (sqrt(g[0]) <= a.tol * nb) {
+                status = COL_CONVERGED;
+                st->rr_true[j] = g[0];
+            } else {
+                status = COL_ACTIVE;
+            }
+        }
+    } else if (phase == MR_SIGMA) {
+        if (status == COL_ACTIVE) {
+            const double sigma = g[0];
+            if (!(sigma > 0.0) || !isfinite(sigma)) status = COL_BREAKDOWN;
+            else st->alpha[j] = st->rho[j] / sigma;
+        }
+    } else if (phase == MR_ITER) {
+        // g = (r'z, r'r) after the update: the oracle's order of tests.
+        if (status == COL_ACTIVE) {
+            st->iters[j] += 1;
+            st->first[j] = 0;
+            st->rr[j] = g[1];
+            if (sqrt(g[1]) <= st->thr[j]) {
+                status = COL_PENDING;
+            } else if (!(g[0] > 0.0) || !isfinite(g[0])) {
+                status = COL_BREAKDOWN;
+            } else if (st->iters[j] >= a.maxit) {
+                status = COL_MAXIT;
+            } else {
+                st->beta[j] = g[0] / st->rho[j];
+                st->rho[j] = g[0];
+            }
+        }
+    } else if (phase == MR_CHECK) {
+        // g = (r'r, r'z, b'b) of the true residual; r, z were replaced for pending columns.
+        if (status == COL_PENDING) {
+            if (sqrt(g[0]) <= st->thr[j]) {
+                status = COL_CONVERGED;
+                st->rr_true[j] = g[0];
+            } else if (!(g[1] > 0.0) || !isfinite(g[1])) {
+                status = COL_BREAKDOWN;
+            } else if (st->iters[j] >= a.maxit) {
+                status = COL_MAXIT;
+            } else {
+                status = COL_ACTIVE;
+                st->repl[j] += 1;
+                st->beta[j] = g[1] / st->rho[j];
+                st->rho[j] = g[1];
+            }
+        }
+    } else {  // MR_REPORT: true residual of the returned x for every column
+        if (j < a.s && status != COL_ZERO) st->rr_true[j] = g[0];
+    }
+    st->status[j] = status;
+    // Flags from wave 0: any column active, any pending.
+    const unsigned long long act = __ballot(status == COL_ACTIVE);
+    const unsigned long long pen = __ballot(status == COL_PENDING);
+    if (j == 0) {
+        st->stop = act == 0ull;
+        st->any_pending = pen != 0ull;
+    }
+}
+
+// x_j = 0 for columns with b_j = 0.
+template <typename T>
+__global__ void k_mr_zero_cols(MrArgs<T> a)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    if (lane >= a.s || a.st->status[lane] != COL_ZERO) return;
+    for (int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < a.n;
+         i += gridDim.x * (blockDim.x / kWave))
+        a.X[(size_t)i * a.s + lane] = T(0);
+}
+
+// Y = A X (row-major N x s), lane = column.
+template <int BS, typename T>
+__global__ __launch_bounds__(BS) void k_spmm(int n, int s, const int* __restrict__ rowptr,
+                                             const int* __restrict__ col, const T* __restrict__ val,
+                                             const T* __restrict__ X, T* __restrict__ Y, int rows_per_block, int G)
+{
+    const int L = mr_logical(G);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int rs = min(L * rows_per_block, n), re = min(rs + rows_per_block, n);
+    const int cl = lane < s ? lane : 0;
+    for (int i = rs + w; i < re; i += BS / kWave) {
+        const T y = mr_row<T>(rowptr, col, val, i, [&](int j) { return X[(size_t)j * s + cl]; });
+        if (lane < s) Y[(size_t)i * s + lane] = y;
+    }
+}
+
+constexpr int kMrBS = 512;
+
+}  // namespace jpcg
+
+// Multi-RHS solver state hanging off a context, for one block width s.
+struct cg_multi {
+    int s = 0, G = 0, chunk = 0;
+    double* work = nullptr;  // R, Z, P0, P1, Q, and the solver's own B, X: 7 N s doubles
+    double* part = nullptr;
+    jpcg::MrState* st = nullptr;
+    jpcg::MrState* hst = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipEvent_t ev = nullptr;
+    jpcg::MrArgs<double> args{};
+};
+
+namespace jpcg {
+
+static void destroy_multi(cg_multi* m)
+{
+    if (!m) return;
+    for (auto& e : m->exec)
+        if (e) (void)hipGraphExecDestroy(e);
+    if (m->ev) (void)hipEventDestroy(m->ev);
+    if (m->work) (void)hipFree(m->work);
+    if (m->part) (void)hipFree(m->part);
+    if (m->st) (void)hipFree(m->st);
+    if (m->hst) (void)hipHostFree(m->hst);
+    delete m;
+}
+
+static void mr_launch(const void* fn, int grid, int bs, hipStream_t st, void** args)
+{
+    JPCG_HIP(hipLaunchKernel(fn, dim3(grid), dim3(bs), args, 0, st));
+}
+
+static cg_multi* make_multi(cg_ctx* c, int s)
+{
+    cg_multi* m = new cg_multi();
+    try {
+        m->s = s;
+        m->chunk = 8;
+        m->G = std::max(8, std::min(c->cus * 2, (c->n + 63) / 64) / 8 * 8);
+        const size_t ns = (size_t)c->n * s;
+        JPCG_HIP(hipMalloc(&m->work, sizeof(double) * ns * 7));
+        JPCG_HIP(hipMalloc(&m->part, sizeof(double) * (size_t)m->G * 3 * kWave));
+        JPCG_HIP(hipMalloc(&m->st, sizeof(MrState)));
+        JPCG_HIP(hipHostMalloc(&m->hst, sizeof(MrState), hipHostMallocDefault));
+        JPCG_HIP(hipEventCreateWithFlags(&m->ev, hipEventDisableTiming));
+        JPCG_HIP(hipMemsetAsync(m->work, 0, sizeof(double) * ns * 7, c->stream));
+        JPCG_HIP(hipMemsetAsync(m->st, 0, sizeof(MrState), c->stream));
+        MrArgs<double>& a = m->args;
+        a.n = c->n;
+        a.s = s;
+        a.rowptr = c->rowptr;
+        a.col = c->col;
+        a.val = c->val;
+        a.dinv = c->dinv;
+        a.R = m->work;
+        a.Z = m->work + ns;
+        a.P[0] = m->work + 2 * ns;
+        a.P[1] = m->work + 3 * ns;
+        a.Q = m->work + 4 * ns;
+        a.B = m->work + 5 * ns;
+        a.X = m->work + 6 * ns;
+        a.G = m->G;
+        a.rows_per_block = (c->n + m->G - 1) / m->G;
+        a.part = m->part;
+        a.st = m->st;
+        a.maxit = c->n;
+        a.tol = 1e-10;
+        JPCG_HIP(hipStreamSynchronize(c->stream));
+        return m;
+    } catch (...) {
+        destroy_multi(m);
+        throw;
+    }
+}
+
+// (Re)capture the chunk graphs; tol and maxit are kernel arguments.
+static void capture_multi(cg_multi* m)
+{
+    for (auto& e : m->exec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    hipStream_t cap;
+    JPCG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    for (int par = 0; par < 2; ++par) {
+        hipGraph_t graph;
+        JPCG_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        for (int it = 0; it < m->chunk; ++it) {
+            int P = (par + it) & 1, ph_sig = MR_SIGMA, ph_it = MR_ITER;
+            void* a0[] = {&m->args, &P};
+            mr_launch((const void*)k_mr_direction<kMrBS, double>, m->G, kMrBS, cap, a0);
+            void* a1[] = {&m->args, &ph_sig};
+            mr_launch((const void*)k_mr_scalars<double>, 1, 256, cap, a1);
+            mr_launch((const void*)k_mr_update<kMrBS, double>, m->G, kMrBS, cap, a0);
+            void* a2[] = {&m->args, &ph_it};
+            mr_launch((const void*)k_mr_scalars<double>, 1, 256, cap, a2);
+        }
+        JPCG_HIP(hipStreamEndCapture(cap, &graph));
+        hipError_t e = hipGraphInstantiate(&m->exec[par], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        JPCG_HIP(e);
+    }
+    JPCG_HIP(hipStreamDestroy(cap));
+}
+
+void free_multi(cg_ctx* c)
+{
+    destroy_multi(c->multi);
+    c->multi = nullptr;
+}
+
+static MrState mr_read(cg_ctx* c, cg_multi* m)
+{
+    JPCG_HIP(hipMemcpyAsync(m->hst, m->st, sizeof(MrState), hipMemcpyDeviceToHost, c->stream));
+    JPCG_HIP(hipStreamSynchronize(c->stream));
+    return *m->hst;
+}
+
+}  // namespace jpcg
+
+using namespace jpcg;
+
+extern "C" {
+
+int spmm(cg_ctx* c, const double* X, double* Y, int32_t s)
+{
+    if (!c) return CG_EINVAL;
+    if (!X || !Y || X == Y || s < 1 || s > kCols) return set_error(c, CG_EINVAL, "spmm: bad arguments");
+    try {
+        const int G = std::max(8, std::min(c->cus * 4, (c->n + 15) / 16) / 8 * 8);
+        const int rpb = (c->n + G - 1) / G;
+        int n = c->n;
+        void* args[] = {&n, &s, &c->rowptr, &c->col, &c->val, &X, &Y, (void*)&rpb, (void*)&G};
+        mr_launch((const void*)k_spmm<kMrBS, double>, G, kMrBS, c->stream, args);
+        return 0;
+    } catch (const HipError& e) {
+        return set_error(c, CG_EHIP, std::string("spmm: ") + e.what + ": " + hipGetErrorString(e.code));
+    }
+}
+
+int cg_solve_multi(cg_ctx* c, const double* B, double* X, int32_t s, double tol, int32_t maxit, cg_info* info)
+{
+    if (!c) return CG_EINVAL;
+    if (!B || !X || B == X || s < 1 || s > kCols || !(tol >= 0.0) || !std::isfinite(tol))
+        return set_error(c, CG_EINVAL, "cg_solve_multi: bad arguments");
+    if (maxit <= 0) maxit = c->n;
+    try {
+        if (!c->multi || c->multi->s != s) {
+            destroy_multi(c->multi);
+            c->multi = nullptr;
+            c->multi = make_multi(c, s);
+        }
+        cg_multi* m = c->multi;
+        if (!m->exec[0] || m->args.tol != tol || m->args.maxit != maxit) {
+            m->args.tol = tol;
+            m->args.maxit = maxit;
+            capture_multi(m);
+        }
+        hipStream_t st = c->stream;
+        const size_t nb = sizeof(double) * (size_t)c->n * s;
+        JPCG_HIP(hipEventRecord(c->ev0, st));
+        JPCG_HIP(hipMemcpyAsync((void*)m->args.B, B, nb, hipMemcpyDeviceToDevice, st));
+        JPCG_HIP(hipMemcpyAsync(m->args.X, X, nb, hipMemcpyDeviceToDevice, st));
+        int mode = 0, ph = MR_SETUP;
+        void* ra[] = {&m->args, &mode};
+        mr_launch((const void*)k_mr_residual<kMrBS, double>, m->G, kMrBS, st, ra);
+        void* sa[] = {&m->args, &ph};
+        mr_launch((const void*)k_mr_scalars<double>, 1, 256, st, sa);
+        void* za[] = {&m->args};
+        mr_launch((const void*)k_mr_zero_cols<double>, 256, 256, st, za);
+        int next = 1;
+        const long long guard = 4LL * maxit + 64;
+        long long launched = 0;
+        while (true) {
+            MrState h = mr_read(c, m);
+            if (h.stop) {
+                if (!h.any_pending) break;
+                mode = 1;
+                ph = MR_CHECK;
+                mr_launch((const void*)k_mr_residual<kMrBS, double>, m->G, kMrBS, st, ra);
+                mr_launch((const void*)k_mr_scalars<double>, 1, 256, st, sa);
+                continue;
+            }
+            if (launched > guard) throw HipError{hipErrorUnknown, "multi-RHS solver did not stop"};
+            // Two chunks per poll keep the device busy while the host reads.
+            JPCG_HIP(hipGraphLaunch(m->exec[next & 1], st));
+            next += m->chunk;
+            JPCG_HIP(hipGraphLaunch(m->exec[next & 1], st));
+            next += m->chunk;
+            launched += 2 * m->chunk;
+        }
+        mode = 2;
+        ph = MR_REPORT;
+        mr_launch((const void*)k_mr_residual<kMrBS, double>, m->G, kMrBS, st, ra);
+        mr_launch((const void*)k_mr_scalars<double>, 1, 256, st, sa);
+        JPCG_HIP(hipMemcpyAsync(X, m->args.X, nb, hipMemcpyDeviceToDevice, st));
+        JPCG_HIP(hipEventRecord(c->ev1, st));
+        const MrState h = mr_read(c, m);
+        float ms = 0.f;
+        JPCG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        int worst = CG_CONVERGED;
+        for (int j = 0; j < s; ++j) {
+            int code = CG_CONVERGED;
+            if (h.status[j] == COL_MAXIT) code = CG_MAXIT;
+            else if (h.status[j] == COL_BREAKDOWN) code = CG_BREAKDOWN;
+            worst = std::max(worst, code);
+            if (info) {
+                cg_info& o = info[j];
+                o.iters = h.iters[j];
+                o.status = code;
+                o.replacements = h.repl[j];
+                o.outer = 0;
+                o.relres_recur = h.nb[j] > 0 ? std::sqrt(h.rr[j]) / h.nb[j] : 0.0;
+                o.relres_true = h.nb[j] > 0 ? std::sqrt(h.rr_true[j]) / h.nb[j] : 0.0;
+                o.seconds = ms * 1e-3;
+            }
+        }
+        return worst;
+    } catch (const HipError& e) {
+        return set_error(c, CG_EHIP, std::string("cg_solve_multi: ") + e.what + ": " + hipGetErrorString(e.code));
+    }
+}
+
+}  // extern "C"

@@ -28,323 +28,11 @@
 #include <new>
 
 #include "context.hpp"
+#include "sr_kernels.hpp"
+#include "std_kernels.hpp"
 #include "tiles.hpp"
 
 namespace jpcg {
-
-enum StopCode : int {
-    RUNNING = 0,
-    STOP_ZERO_RHS = 1,   // ||b|| = 0: x = 0
-    STOP_CONV0 = 2,      // x0 already satisfies the test
-    STOP_CHECK = 3,      // recurrence residual passed: confirm on b - A x
-    STOP_MAXIT = 4,
-    STOP_BREAKDOWN = 5,
-    STOP_CONVERGED = 6,  // confirmed
-};
-
-struct CgState {
-    int stop;
-    int k;  // completed iterations (advanced by B's workgroup 0)
-    int maxit;
-    int replacements;
-    double nb;       // ||b||
-    double thr;      // tol * ||b||
-    double rho[2];   // rho[k % 2] = r_{k-1}' z_{k-1}, written by A_k
-    double rr;       // ||r_k||^2 seen by the last continue-condition test
-    double rr_true;  // ||b - A x||^2 of the returned x
-    double sigma, alpha, beta;
-};
-
-struct CgArgs {
-    SysView<double> s;  // b, x are the context's copies; p0/p1 alternate by parity
-    TileMap tm;         // tiles of the sparse products, per workgroup
-    int R;              // rows per workgroup of the elementwise update
-    int G;
-    double* part_setup;    // [G][3]: r'r, r'z, b'b of r0
-    double* part_sig;      // [G][1]: p'q
-    double* part_iter[2];  // [G][2]: r'z, r'r after B of parity P (or a check)
-    double* part_rep;      // [G][1]: ||b - A x||^2 for the report
-    CgState* st;
-    double* hist;
-};
-
-template <int NPL, int BS>
-struct Lds {
-    double red[(BS / kWave) * 4];
-    double prod[BS * NPL];  // per wave: 64 * NPL products
-};
-
-template <int NPL>
-__device__ __forceinline__ double* wave_prod(double* prod)
-{
-    return prod + (threadIdx.x / kWave) * (kWave * NPL);
-}
-
-__device__ __forceinline__ int logical(const CgArgs& a) { return xcd_logical_block((int)blockIdx.x, a.G); }
-
-__device__ __forceinline__ bool leader(const CgArgs& a) { return threadIdx.x == 0 && logical(a) == 0; }
-
-struct Pair {
-    double a, b;
-};
-
-// r_out = b - A x and (if z_out) z_out = M^-1 r_out over the workgroup's tiles;
-// shares of r'r, r'z, b'b.
-template <int NPL, int BS>
-__device__ __forceinline__ void tile_residual(const CgArgs& a, double* prod, double* r_out, double* z_out,
-                                              double& rr, double& rz, double& bb)
-{
-    const SysView<double>& s = a.s;
-    const double* __restrict__ x = s.x;
-    tile_rows<NPL, double>(
-        s.rowptr, s.col, s.val, a.tm, logical(a), wave_prod<NPL>(prod), [&](int j) { return x[j]; }, Mul<double>{},
-        [&](int i) { return Pair{s.b[i], s.dinv[i]}; },
-        [&](int i, double ax, Pair bd) {
-            const double bi = bd.a;
-            const double ri = bi - ax;
-            r_out[i] = ri;
-            rr += ri * ri;
-            bb += bi * bi;
-            if (z_out) {
-                const double zi = bd.b * ri;
-                z_out[i] = zi;
-                rz += ri * zi;
-            }
-        },
-        NoPrologue{});
-}
-
-template <int NPL, int BS>
-__global__ __launch_bounds__(BS) void k_setup(CgArgs a)
-{
-    __shared__ Lds<NPL, BS> sh;
-    double v[3] = {0.0, 0.0, 0.0};
-    tile_residual<NPL, BS>(a, sh.prod, a.s.r, a.s.z, v[0], v[1], v[2]);
-    block_partials<BS, 3>(v, sh.red, a.part_setup, logical(a));
-}
-
-// A_1: initial tests, then p_1 = z_0, q = A p_1.
-template <int NPL, int BS>
-__global__ __launch_bounds__(BS) void k_first(CgArgs a, double tol, int maxit)
-{
-    __shared__ Lds<NPL, BS> sh;
-    double g[3];
-    wave_grid_sum<3>(a.part_setup, a.G, g);
-    const double rr = g[0], rho = g[1], nb = sqrt(g[2]), thr = tol * nb;
-    CgState* st = a.st;
-    const SysView<double>& s = a.s;
-    if (leader(a)) {
-        st->k = 0;
-        st->maxit = maxit;
-        st->replacements = 0;
-        st->nb = nb;
-        st->thr = thr;
-        st->rho[1] = rho;
-        st->rr = rr;
-        st->rr_true = -1.0;
-        if (a.hist) a.hist[0] = nb > 0.0 ? sqrt(rr) / nb : 0.0;
-        st->stop = nb == 0.0 ? STOP_ZERO_RHS : (sqrt(rr) <= thr ? STOP_CONV0 : RUNNING);
-        if (nb == 0.0) st->rr_true = 0.0;
-        else if (sqrt(rr) <= thr) st->rr_true = rr;
-    }
-    if (nb == 0.0) {
-        const int L = logical(a);
-        const int rs = min(L * a.R, s.n), re = min(rs + a.R, s.n);
-        for (int i = rs + (int)threadIdx.x; i < re; i += BS) s.x[i] = 0.0;
-        return;
-    }
-    if (sqrt(rr) <= thr) return;
-    const double* __restrict__ z = s.z;
-    double sig = 0.0;
-    tile_rows<NPL, double>(
-        s.rowptr, s.col, s.val, a.tm, logical(a), wave_prod<NPL>(sh.prod), [&](int j) { return z[j]; },
-        Mul<double>{}, [&](int i) { return z[i]; },
-        [&](int i, double qi, double pi) {
-            s.p1[i] = pi;
-            s.q[i] = qi;
-            sig += pi * qi;
-        },
-        NoPrologue{});
-    double v[1] = {sig};
-    block_partials<BS, 1>(v, sh.red, a.part_sig, logical(a));
-}
-
-// A_k, k >= 2, parity P = k % 2.  The scalar work (reducing the previous B's
-// partials, the tests, beta) runs as the tile walk's prologue, after the
-// first gathers are issued, so its memory latency overlaps theirs.
-template <int NPL, int BS>
-__global__ __launch_bounds__(BS) void k_direction(CgArgs a, int P)
-{
-    __shared__ Lds<NPL, BS> sh;
-    CgState* st = a.st;
-    const SysView<double>& s = a.s;
-    const double* __restrict__ z = s.z;
-    const double* __restrict__ pold = P ? s.p0 : s.p1;
-    double* __restrict__ pnew = P ? s.p1 : s.p0;
-    const bool lead = leader(a);
-    double beta = 0.0, sig = 0.0;
-    bool go = true;
-    auto prologue = [&]() -> bool {
-        const int stop = st->stop, km1 = st->k, maxit = st->maxit;
-        const double thr = st->thr, nb = st->nb, rho_prev = st->rho[P ^ 1];
-        double g[2];
-        wave_grid_sum<2>(a.part_iter[P ^ 1], a.G, g);
-        const double rz = g[0], rr = g[1];
-        go = false;
-        if (stop != RUNNING) return false;
-        if (lead) {
-            st->rr = rr;
-            if (a.hist) a.hist[km1] = sqrt(rr) / nb;
-        }
-        // The oracle's order: continue-condition, breakdown of r'z, iteration limit.
-        if (sqrt(rr) <= thr) {
-            if (lead) st->stop = STOP_CHECK;
-            return false;
-        }
-        if (!(rz > 0.0) || !isfinite(rz)) {
-            if (lead) st->stop = STOP_BREAKDOWN;
-            return false;
-        }
-        if (km1 >= maxit) {
-            if (lead) st->stop = STOP_MAXIT;
-            return false;
-        }
-        beta = rz / rho_prev;
-        if (lead) {
-            st->rho[P] = rz;
-            st->beta = beta;
-        }
-        go = true;
-        return true;
-    };
-    tile_rows<NPL, double>(
-        s.rowptr, s.col, s.val, a.tm, logical(a), wave_prod<NPL>(sh.prod),
-        [&](int j) { return Pair{z[j], pold[j]}; },
-        [&](double v, Pair zp) { return v * __builtin_fma(beta, zp.b, zp.a); },
-        [&](int i) { return Pair{z[i], pold[i]}; },
-        [&](int i, double qi, Pair zp) {
-            const double pi = __builtin_fma(beta, zp.b, zp.a);
-            pnew[i] = pi;
-            s.q[i] = qi;
-            sig += pi * qi;
-        },
-        prologue);
-    if (!go) return;  // the same decision in every wave of every workgroup
-    double v[1] = {sig};
-    block_partials<BS, 1>(v, sh.red, a.part_sig, logical(a));
-}
-
-// B_k, parity P = k % 2.  Rows are split arithmetically; the state, the row
-// operands and the partials of sigma are all requested before any is used.
-template <int BS>
-__global__ __launch_bounds__(BS) void k_update(CgArgs a, int P)
-{
-    __shared__ Lds<1, BS> sh;
-    CgState* st = a.st;
-    const SysView<double>& s = a.s;
-    const int stop = st->stop;
-    const double rho = st->rho[P];
-    const int L = logical(a);
-    const int rs = min(L * a.R, s.n), re = min(rs + a.R, s.n);
-    const double* __restrict__ p = P ? s.p1 : s.p0;
-    const int i0 = rs + (int)threadIdx.x;
-    const bool h0 = i0 < re;
-    const int ic = h0 ? i0 : 0;
-    const double p0 = p[ic], q0 = s.q[ic], x0 = s.x[ic], r0 = s.r[ic], d0 = s.dinv[ic];
-    double g[1];
-    wave_grid_sum<1>(a.part_sig, a.G, g);
-    const double sigma = g[0];
-    if (stop != RUNNING) return;
-    const bool lead = leader(a);
-    if (!(sigma > 0.0) || !isfinite(sigma)) {
-        if (lead) st->stop = STOP_BREAKDOWN;
-        return;
-    }
-    const double alpha = rho / sigma;
-    double v[2] = {0.0, 0.0};
-    if (h0) {
-        s.x[i0] = __builtin_fma(alpha, p0, x0);
-        const double ri = __builtin_fma(-alpha, q0, r0);
-        s.r[i0] = ri;
-        const double zi = d0 * ri;
-        s.z[i0] = zi;
-        v[0] += ri * zi;
-        v[1] += ri * ri;
-    }
-    for (int i = i0 + BS; i < re; i += BS) {
-        s.x[i] = __builtin_fma(alpha, p[i], s.x[i]);
-        const double ri = __builtin_fma(-alpha, s.q[i], s.r[i]);
-        s.r[i] = ri;
-        const double zi = s.dinv[i] * ri;
-        s.z[i] = zi;
-        v[0] += ri * zi;
-        v[1] += ri * ri;
-    }
-    block_partials<BS, 2>(v, sh.red, a.part_iter[P], L);
-    if (lead) {
-        st->k = st->k + 1;
-        st->sigma = sigma;
-        st->alpha = alpha;
-    }
-}
-
-// True residual r = b - A x, z = M^-1 r into the slot the next A_{k+1} reads.
-template <int NPL, int BS>
-__global__ __launch_bounds__(BS) void k_check(CgArgs a, int P)
-{
-    __shared__ Lds<NPL, BS> sh;
-    double rr = 0.0, rz = 0.0, bb = 0.0;
-    tile_residual<NPL, BS>(a, sh.prod, a.s.r, a.s.z, rr, rz, bb);
-    double v[2] = {rz, rr};
-    block_partials<BS, 2>(v, sh.red, a.part_iter[P], logical(a));
-}
-
-// One workgroup: accept the solve, or resume with the replaced residual.
-template <int BS>
-__global__ __launch_bounds__(BS) void k_check_decide(CgArgs a, int P)
-{
-    double g[2];
-    wave_grid_sum<2>(a.part_iter[P], a.G, g);
-    if (threadIdx.x == 0) {
-        CgState* st = a.st;
-        if (sqrt(g[1]) <= st->thr) {
-            st->stop = STOP_CONVERGED;
-            st->rr_true = g[1];
-        } else {
-            st->stop = RUNNING;
-            st->replacements += 1;
-        }
-    }
-}
-
-// ||b - A x||^2 of the returned x, for solves that end without convergence.
-template <int NPL, int BS>
-__global__ __launch_bounds__(BS) void k_report(CgArgs a)
-{
-    __shared__ Lds<NPL, BS> sh;
-    double v[1] = {0.0};
-    double rz = 0.0, bb = 0.0;
-    tile_residual<NPL, BS>(a, sh.prod, a.s.q, (double*)nullptr, v[0], rz, bb);
-    block_partials<BS, 1>(v, sh.red, a.part_rep, logical(a));
-}
-
-template <int BS>
-__global__ __launch_bounds__(BS) void k_report_sum(CgArgs a)
-{
-    double g[1];
-    wave_grid_sum<1>(a.part_rep, a.G, g);
-    if (threadIdx.x == 0) a.st->rr_true = g[0];
-}
-
-// y = A x over the solver's tiles (rows summed in stored order).
-template <int NPL, int BS>
-__global__ __launch_bounds__(BS) void k_spmv(CgArgs a, const double* __restrict__ x, double* __restrict__ y)
-{
-    __shared__ Lds<NPL, BS> sh;
-    tile_rows<NPL, double>(a.s.rowptr, a.s.col, a.s.val, a.tm, logical(a), wave_prod<NPL>(sh.prod),
-                           [&](int j) { return x[j]; }, Mul<double>{}, NoPre{},
-                           [&](int i, double v, int) { y[i] = v; }, NoPrologue{});
-}
 
 // dinv_i = 1 / a_ii (Jacobi) or 1 (no preconditioner); flags a missing or
 // non-positive diagonal.
@@ -370,6 +58,17 @@ __global__ void jacobi_kernel(int n, const int* __restrict__ rowptr, const int* 
     if (dinv32) dinv32[i] = (float)inv;
 }
 
+// s_i = sum_j a_ij in FP64, stored in FP32, for the row-sum-preserving FP32 product.
+__global__ void rowsum_kernel(int n, const int* __restrict__ rowptr, const double* __restrict__ val,
+                              float* __restrict__ rs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) s += val[k];
+    rs[i] = (float)s;
+}
+
 __global__ void cast_f32_kernel(int64_t n, const double* __restrict__ in, float* __restrict__ out)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -379,6 +78,42 @@ __global__ void cast_f32_kernel(int64_t n, const double* __restrict__ in, float*
 // ---------------------------------------------------------------------------
 // Kernel tables per launch shape
 // ---------------------------------------------------------------------------
+// FP64 refinement step of the mixed-precision form: every workgroup reduces
+// the partials of r'r and b'b of r = b - A x (FP64) and scales the residual
+// into the FP32 right-hand side, b32 = r / ||r||, clearing x32.
+struct MixedState {
+    double rr, bb, scale;
+};
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_mixed_scale(int n, const double* __restrict__ r, const double* part, int G,
+                                                    float* __restrict__ b32, float* __restrict__ x32,
+                                                    MixedState* ms)
+{
+    double g[3];
+    wave_grid_sum<3>(part, G, g);  // r'r, r'z, b'b of the FP64 residual
+    const double nr = sqrt(g[0]);
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ms->rr = g[0];
+        ms->bb = g[2];
+        ms->scale = nr;
+    }
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) {
+        b32[i] = (float)(r[i] * inv);
+        x32[i] = 0.0f;
+    }
+}
+
+// x64 += ||r|| * x32: the FP64 refinement update.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_mixed_update(int n, double* __restrict__ x, const float* __restrict__ x32,
+                                                     const MixedState* ms)
+{
+    const double sc = ms->scale;
+    for (int i = blockIdx.x * BS + threadIdx.x; i < n; i += gridDim.x * BS) x[i] = fma(sc, (double)x32[i], x[i]);
+}
+
 struct CgKernels {
     const void* spmv;
     const void* setup;
@@ -389,30 +124,52 @@ struct CgKernels {
     const void* check_decide;
     const void* report;
     const void* report_sum;
+    // single-reduction form (FP64 only)
+    const void* sr_setup;
+    const void* sr_first;
+    const void* sr_iter;
+    const void* sr_residual;
+    const void* sr_decide;
+    const void* sr_restart;
 };
 
-template <int NPL, int BS>
+template <int NPL, int BS, typename T>
 static CgKernels kernels_for()
 {
-    return CgKernels{(const void*)k_spmv<NPL, BS>,      (const void*)k_setup<NPL, BS>,
-                     (const void*)k_first<NPL, BS>,     (const void*)k_direction<NPL, BS>,
-                     (const void*)k_update<BS>,         (const void*)k_check<NPL, BS>,
-                     (const void*)k_check_decide<BS>,   (const void*)k_report<NPL, BS>,
-                     (const void*)k_report_sum<BS>};
+    CgKernels k{};
+    k.spmv = (const void*)k_spmv<NPL, BS, T>;
+    k.setup = (const void*)k_setup<NPL, BS, T>;
+    k.first = (const void*)k_first<NPL, BS, T>;
+    k.direction = (const void*)k_direction<NPL, BS, T>;
+    k.update = (const void*)k_update<BS, T>;
+    k.check = (const void*)k_check<NPL, BS, T>;
+    k.check_decide = (const void*)k_check_decide<BS, T>;
+    k.report = (const void*)k_report<NPL, BS, T>;
+    k.report_sum = (const void*)k_report_sum<BS, T>;
+    if constexpr (sizeof(T) == 8) {
+        k.sr_setup = (const void*)k_sr_setup<NPL, BS>;
+        k.sr_first = (const void*)k_sr_first<NPL, BS>;
+        k.sr_iter = (const void*)k_sr_iter<NPL, BS>;
+        k.sr_residual = (const void*)k_sr_residual<NPL, BS>;
+        k.sr_decide = (const void*)k_sr_decide<BS>;
+        k.sr_restart = (const void*)k_sr_restart<NPL, BS>;
+    }
+    return k;
 }
 
 // Tile shapes: NPL nonzeros per lane, BS threads; LDS for products is
-// BS * NPL * 8 bytes, kept within 64 KiB.
-static bool kernels(int npl, int bs, CgKernels& k)
+// BS * NPL * sizeof(T) bytes.
+template <typename T>
+static bool kernels_t(int npl, int bs, CgKernels& k)
 {
-    if (npl == 4 && bs == 256) { k = kernels_for<4, 256>(); return true; }
-    if (npl == 8 && bs == 256) { k = kernels_for<8, 256>(); return true; }
-    if (npl == 16 && bs == 256) { k = kernels_for<16, 256>(); return true; }
-    if (npl == 4 && bs == 512) { k = kernels_for<4, 512>(); return true; }
-    if (npl == 8 && bs == 512) { k = kernels_for<8, 512>(); return true; }
-    if (npl == 16 && bs == 512) { k = kernels_for<16, 512>(); return true; }
-    if (npl == 4 && bs == 1024) { k = kernels_for<4, 1024>(); return true; }
-    if (npl == 8 && bs == 1024) { k = kernels_for<8, 1024>(); return true; }
+    if (npl == 4 && bs == 256) { k = kernels_for<4, 256, T>(); return true; }
+    if (npl == 8 && bs == 256) { k = kernels_for<8, 256, T>(); return true; }
+    if (npl == 16 && bs == 256) { k = kernels_for<16, 256, T>(); return true; }
+    if (npl == 4 && bs == 512) { k = kernels_for<4, 512, T>(); return true; }
+    if (npl == 8 && bs == 512) { k = kernels_for<8, 512, T>(); return true; }
+    if (npl == 16 && bs == 512) { k = kernels_for<16, 512, T>(); return true; }
+    if (npl == 4 && bs == 1024) { k = kernels_for<4, 1024, T>(); return true; }
+    if (npl == 8 && bs == 1024) { k = kernels_for<8, 1024, T>(); return true; }
     return false;
 }
 
@@ -448,28 +205,37 @@ int set_error(cg_ctx* c, int code, const std::string& msg)
     return code;
 }
 
-// Per-grid device buffers: partials and tiles.
-struct GridBufs {
-    int G = 0;
-    int T = 0;
-    int4* tiles = nullptr;   // [T]
-    double* part = nullptr;  // setup 3G + sig G + iter 2*2G + rep G = 9G
+// What a solve leaves behind, for either form.
+struct SolveResult {
+    int stop = 0;
+    int iters = 0;
+    int replacements = 0;
+    double nb = 0.0, rr = 0.0, rr_true = 0.0;
 };
 
 }  // namespace jpcg
 
-// The graph-chunked solver state that hangs off a context.
+// The graph-chunked solver state that hangs off a context: one form, one
+// precision (FP64, or the FP32 inner solver of the mixed form), one launch
+// shape.
 struct cg_graphs {
     jpcg::CgKernels kern{};
-    int npl = 0, bs = 0, G = 0, chunk = 0;
-    jpcg::GridBufs gb;
-    jpcg::CgState* st = nullptr;
-    jpcg::CgState* hst = nullptr;  // pinned, 4 slots
-    double* cb = nullptr;          // context-owned b and x: graphs bind fixed addresses
-    double* cx = nullptr;
+    int form = CG_FORM_STANDARD;
+    bool fp32 = false;
+    int npl = 0, bs = 0, G = 0, T = 0, chunk = 0;
+    int4* tiles = nullptr;
+    double* part = nullptr;  // 9G doubles, laid out per form
+    void* st = nullptr;      // CgState or SrState
+    void* hst = nullptr;     // pinned, 4 slots
+    size_t st_bytes = 0;
+    void* cb = nullptr;      // the solver's own b and x: graphs bind fixed addresses
+    void* cx = nullptr;
+    void* work32 = nullptr;  // FP32 work vectors (5n floats)
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipEvent_t evs[4] = {nullptr, nullptr, nullptr, nullptr};
-    jpcg::CgArgs args{};
+    jpcg::CgArgsT<double> args{};
+    jpcg::CgArgsT<float> args32{};
+    jpcg::SrArgs sargs{};
 };
 
 namespace jpcg {
@@ -481,20 +247,39 @@ static void destroy_graphs(cg_graphs* g)
         if (e) (void)hipGraphExecDestroy(e);
     for (auto& e : g->evs)
         if (e) (void)hipEventDestroy(e);
-    void* ptrs[] = {g->gb.tiles, g->gb.part, g->st, g->cb, g->cx};
+    void* ptrs[] = {g->tiles, g->part, g->st, g->cb, g->cx, g->work32};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (g->hst) (void)hipHostFree(g->hst);
     delete g;
 }
 
-// Build the kernels' arguments and capture the two chunk graphs (first A of
-// parity 0 or 1) for one launch shape.
-static cg_graphs* make_graphs(cg_ctx* c, int npl, int bs, int G, int chunk)
+template <typename T>
+static void fill_args(CgArgsT<T>& a, const SysView<T>& s, const TileMap& tm, int n, int G, double* part, void* st)
+{
+    a.s = s;
+    a.tm = tm;
+    a.R = (n + G - 1) / G;
+    a.G = G;
+    a.part_setup = part;
+    a.part_sig = part + 3 * (size_t)G;
+    a.part_iter[0] = part + 4 * (size_t)G;
+    a.part_iter[1] = part + 6 * (size_t)G;
+    a.part_rep = part + 8 * (size_t)G;
+    a.st = (CgState*)st;
+    a.hist = nullptr;
+}
+
+// Build the kernels' arguments and capture the two chunk graphs (first
+// iteration of parity 0 or 1) for one form, precision and launch shape.
+static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, int G, int chunk)
 {
     cg_graphs* g = new cg_graphs();
     try {
-        if (!kernels(npl, bs, g->kern)) throw HipError{hipErrorInvalidValue, "launch shape"};
+        const bool ok = fp32 ? kernels_t<float>(npl, bs, g->kern) : kernels_t<double>(npl, bs, g->kern);
+        if (!ok || (fp32 && form != CG_FORM_STANDARD)) throw HipError{hipErrorInvalidValue, "launch shape"};
+        g->form = form;
+        g->fp32 = fp32;
         g->npl = npl;
         g->bs = bs;
         g->G = G;
@@ -502,29 +287,60 @@ static cg_graphs* make_graphs(cg_ctx* c, int npl, int bs, int G, int chunk)
         std::vector<int4> tiles;
         build_tiles(c->h_rowptr, kWave * npl, tiles);
         const int T = (int)tiles.size();
-        g->gb.G = G;
-        g->gb.T = T;
-        JPCG_HIP(hipMalloc(&g->gb.tiles, sizeof(int4) * std::max(T, 1)));
-        JPCG_HIP(hipMalloc(&g->gb.part, sizeof(double) * 9 * (size_t)G));
-        JPCG_HIP(hipMalloc(&g->st, sizeof(CgState)));
-        JPCG_HIP(hipHostMalloc(&g->hst, sizeof(CgState) * 4, hipHostMallocDefault));
-        JPCG_HIP(hipMalloc(&g->cb, sizeof(double) * c->n));
-        JPCG_HIP(hipMalloc(&g->cx, sizeof(double) * c->n));
+        g->T = T;
+        g->st_bytes = std::max(sizeof(CgState), sizeof(SrState));
+        const size_t eb = fp32 ? sizeof(float) : sizeof(double);
+        JPCG_HIP(hipMalloc(&g->tiles, sizeof(int4) * std::max(T, 1)));
+        JPCG_HIP(hipMalloc(&g->part, sizeof(double) * 9 * (size_t)G));
+        JPCG_HIP(hipMalloc(&g->st, g->st_bytes));
+        JPCG_HIP(hipHostMalloc(&g->hst, g->st_bytes * 4, hipHostMallocDefault));
+        JPCG_HIP(hipMalloc(&g->cb, eb * c->n));
+        JPCG_HIP(hipMalloc(&g->cx, eb * c->n));
         for (auto& e : g->evs) JPCG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        if (T) JPCG_HIP(hipMemcpyAsync(g->gb.tiles, tiles.data(), sizeof(int4) * T, hipMemcpyHostToDevice, c->stream));
-        JPCG_HIP(hipMemsetAsync(g->st, 0, sizeof(CgState), c->stream));
-        CgArgs& a = g->args;
-        a.s = SysView<double>{c->n, c->rowptr, c->col, c->val, c->dinv, g->cb, g->cx, c->r, c->z, c->p0, c->p1, c->q};
-        a.tm = TileMap{g->gb.tiles, T, (T + G - 1) / G};
-        a.R = (c->n + G - 1) / G;
-        a.G = G;
-        a.part_setup = g->gb.part;
-        a.part_sig = g->gb.part + 3 * (size_t)G;
-        a.part_iter[0] = g->gb.part + 4 * (size_t)G;
-        a.part_iter[1] = g->gb.part + 6 * (size_t)G;
-        a.part_rep = g->gb.part + 8 * (size_t)G;
-        a.st = g->st;
-        a.hist = nullptr;
+        if (T) JPCG_HIP(hipMemcpyAsync(g->tiles, tiles.data(), sizeof(int4) * T, hipMemcpyHostToDevice, c->stream));
+        JPCG_HIP(hipMemsetAsync(g->st, 0, g->st_bytes, c->stream));
+        const TileMap tm{g->tiles, T, (T + G - 1) / G};
+        if (fp32) {
+            JPCG_HIP(hipMalloc(&g->work32, sizeof(float) * 5 * (size_t)c->n));
+            JPCG_HIP(hipMemsetAsync(g->work32, 0, sizeof(float) * 5 * (size_t)c->n, c->stream));
+            float* w = (float*)g->work32;
+            const size_t n = c->n;
+            fill_args(g->args32,
+                      SysView<float>{c->n, c->rowptr, c->col, c->val32, c->dinv32, (float*)g->cb, (float*)g->cx, w,
+                                     w + n, w + 2 * n, w + 3 * n, w + 4 * n},
+                      tm, c->n, G, g->part, g->st);
+            g->args32.rowsum = c->rowsum32;
+        } else {
+            double* const* w = c->work;
+            fill_args(g->args,
+                      SysView<double>{c->n, c->rowptr, c->col, c->val, c->dinv, (double*)g->cb, (double*)g->cx, w[0],
+                                      w[1], w[2], w[3], w[4]},
+                      tm, c->n, G, g->part, g->st);
+            g->args.rowsum = nullptr;
+            SrArgs& sa = g->sargs;
+            sa.n = c->n;
+            sa.rowptr = c->rowptr;
+            sa.col = c->col;
+            sa.val = c->val;
+            sa.dinv = c->dinv;
+            sa.b = (double*)g->cb;
+            sa.x = (double*)g->cx;
+            sa.R[0] = w[0];
+            sa.R[1] = w[1];
+            sa.W[0] = w[2];
+            sa.W[1] = w[3];
+            sa.S[0] = w[4];
+            sa.S[1] = w[5];
+            sa.p = w[6];
+            sa.tm = tm;
+            sa.G = G;
+            sa.part[0] = g->part;
+            sa.part[1] = g->part + 3 * (size_t)G;
+            sa.part_setup = g->part + 6 * (size_t)G;
+            sa.part_chk = g->part + 8 * (size_t)G;
+            sa.st = (SrState*)g->st;
+            sa.hist = nullptr;
+        }
         JPCG_HIP(hipStreamSynchronize(c->stream));
         hipStream_t cap;
         JPCG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -533,9 +349,14 @@ static cg_graphs* make_graphs(cg_ctx* c, int npl, int bs, int G, int chunk)
             JPCG_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
             for (int it = 0; it < chunk; ++it) {
                 int P = (par + it) & 1;
-                void* args[] = {&a, &P};
-                launch(g->kern.direction, G, bs, cap, args);
-                launch(g->kern.update, G, bs, cap, args);
+                if (form == CG_FORM_SINGLE_REDUCTION) {
+                    void* args[] = {&g->sargs, &P};
+                    launch(g->kern.sr_iter, G, bs, cap, args);
+                } else {
+                    void* args[] = {fp32 ? (void*)&g->args32 : (void*)&g->args, &P};
+                    launch(g->kern.direction, G, bs, cap, args);
+                    launch(g->kern.update, G, bs, cap, args);
+                }
             }
             JPCG_HIP(hipStreamEndCapture(cap, &graph));
             hipError_t e = hipGraphInstantiate(&g->exec[par], graph, nullptr, nullptr, 0);
@@ -557,19 +378,66 @@ static void launch_spmv(cg_ctx* c, const double* x, double* y)
     launch(g->kern.spmv, g->G, g->bs, c->stream, args);
 }
 
-// One solve through the graph path.  b, x are caller device pointers.
-static void run_solve(cg_ctx* c, cg_graphs* g, const double* b, double* x, double tol, int maxit, double* hist,
-                      CgState& out)
+// The chunk loop shared by both forms: two chunks in flight; the state block
+// of the older one is inspected while the newer runs.  `iteration` launches
+// one iteration without a graph (used when history is recorded), `stopped`
+// handles a raised stop flag and returns the next iteration index to resume
+// at, or -1 when the solve is over.
+template <typename Iter, typename Stopped>
+static void chunk_loop(cg_ctx* c, cg_graphs* g, int first_k, int maxit, bool use_graph, Iter iteration,
+                       Stopped stopped)
 {
     hipStream_t s = c->stream;
-    const size_t vb = sizeof(double) * c->n;
-    JPCG_HIP(hipMemcpyAsync(g->cb, b, vb, hipMemcpyDeviceToDevice, s));
-    JPCG_HIP(hipMemcpyAsync(g->cx, x, vb, hipMemcpyDeviceToDevice, s));
-    CgArgs a = g->args;
+    int next_k = first_k, slot = 0, pending = 0;
+    const long long guard = (long long)maxit + 8LL * g->chunk + 64;
+    long long launched = 0;
+    char* hst = (char*)g->hst;
+    while (true) {
+        if (use_graph) {
+            JPCG_HIP(hipGraphLaunch(g->exec[next_k & 1], s));
+        } else {
+            for (int it = 0; it < g->chunk; ++it) iteration((next_k + it) & 1);
+        }
+        JPCG_HIP(hipMemcpyAsync(hst + slot * g->st_bytes, g->st, g->st_bytes, hipMemcpyDeviceToHost, s));
+        JPCG_HIP(hipEventRecord(g->evs[slot], s));
+        next_k += g->chunk;
+        launched += g->chunk;
+        slot = (slot + 1) & 3;
+        ++pending;
+        if (pending < 2) continue;
+        const int old = (slot + 2) & 3;  // the chunk launched before the newest
+        JPCG_HIP(hipEventSynchronize(g->evs[old]));
+        --pending;
+        if (*(const int*)(hst + old * g->st_bytes) == RUNNING) {
+            if (launched > guard) throw HipError{hipErrorUnknown, "solver did not stop"};
+            continue;
+        }
+        JPCG_HIP(hipStreamSynchronize(s));  // drain the chunk still in flight
+        pending = 0;
+        const int resume = stopped();
+        if (resume < 0) return;
+        next_k = resume;
+    }
+}
+
+template <typename State>
+static State read_state(cg_ctx* c, cg_graphs* g)
+{
+    State* h = (State*)g->hst;
+    JPCG_HIP(hipMemcpyAsync(h, g->st, sizeof(State), hipMemcpyDeviceToHost, c->stream));
+    JPCG_HIP(hipStreamSynchronize(c->stream));
+    return *h;
+}
+
+// Standard form on the graphs' own b and x.  With confirm == false (the
+// FP32 inner solve of the mixed form) a passed continue-condition ends the
+// solve without the true-residual check.
+template <typename T>
+static SolveResult run_standard(cg_ctx* c, cg_graphs* g, CgArgsT<T> a, double tol, int maxit, double* hist,
+                                bool confirm)
+{
+    hipStream_t s = c->stream;
     a.hist = hist;
-    // The chunk graphs were captured without the history pointer; a solve that
-    // records history launches the same kernels one by one instead.
-    const bool use_graph = hist == nullptr;
     {
         void* args0[] = {&a};
         launch(g->kern.setup, g->G, g->bs, s, args0);
@@ -579,74 +447,166 @@ static void run_solve(cg_ctx* c, cg_graphs* g, const double* b, double* x, doubl
         void* args2[] = {&a, &P};
         launch(g->kern.update, g->G, g->bs, s, args2);
     }
-    int next_k = 2;  // index of the next A to launch
-    int slot = 0, pending = 0;
-    const long long guard = (long long)maxit + 8LL * g->chunk + 64;
-    long long launched = 1;
-    auto launch_chunk = [&](int k0) {
-        if (use_graph) {
-            JPCG_HIP(hipGraphLaunch(g->exec[k0 & 1], s));
-        } else {
-            for (int it = 0; it < g->chunk; ++it) {
-                int P = (k0 + it) & 1;
-                void* args[] = {&a, &P};
-                launch(g->kern.direction, g->G, g->bs, s, args);
-                launch(g->kern.update, g->G, g->bs, s, args);
-            }
-        }
-        JPCG_HIP(hipMemcpyAsync(&g->hst[slot], g->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-        JPCG_HIP(hipEventRecord(g->evs[slot], s));
+    auto iteration = [&](int P) {
+        void* args[] = {&a, &P};
+        launch(g->kern.direction, g->G, g->bs, s, args);
+        launch(g->kern.update, g->G, g->bs, s, args);
     };
-    while (true) {
-        // Keep two chunks in flight; inspect the older one's state.
-        launch_chunk(next_k);
-        next_k += g->chunk;
-        launched += g->chunk;
-        slot = (slot + 1) & 3;
-        ++pending;
-        if (pending < 2) continue;
-        const int old = (slot + 2) & 3;  // the chunk launched before the newest
-        JPCG_HIP(hipEventSynchronize(g->evs[old]));
-        --pending;
-        const CgState& hs = g->hst[old];
-        if (hs.stop == RUNNING) {
-            if (launched > guard) throw HipError{hipErrorUnknown, "solver did not stop"};
-            continue;
-        }
-        // Drain, then read the settled state.
-        JPCG_HIP(hipMemcpyAsync(&g->hst[slot], g->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-        JPCG_HIP(hipStreamSynchronize(s));
-        pending = 0;
-        CgState st = g->hst[slot];
-        if (st.stop == STOP_CHECK) {
+    auto stopped = [&]() -> int {
+        CgState st = read_state<CgState>(c, g);
+        if (st.stop == STOP_CHECK && confirm) {
             int P = st.k & 1;
             void* args[] = {&a, &P};
             launch(g->kern.check, g->G, g->bs, s, args);
             launch(g->kern.check_decide, 1, g->bs, s, args);
-            JPCG_HIP(hipMemcpyAsync(&g->hst[slot], g->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-            JPCG_HIP(hipStreamSynchronize(s));
-            st = g->hst[slot];
-            if (st.stop == RUNNING) {  // replaced residual: resume at A_{k+1}
-                next_k = st.k + 1;
-                continue;
-            }
+            st = read_state<CgState>(c, g);
+            if (st.stop == RUNNING) return st.k + 1;  // replaced residual: resume at A_{k+1}
         }
-        if (st.stop == STOP_MAXIT || st.stop == STOP_BREAKDOWN) {
+        if (confirm && (st.stop == STOP_MAXIT || st.stop == STOP_BREAKDOWN)) {
             void* args[] = {&a};
             launch(g->kern.report, g->G, g->bs, s, args);
             launch(g->kern.report_sum, 1, g->bs, s, args);
         }
-        break;
-    }
-    JPCG_HIP(hipMemcpyAsync(x, g->cx, vb, hipMemcpyDeviceToDevice, s));
-    JPCG_HIP(hipMemcpyAsync(&g->hst[0], g->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    JPCG_HIP(hipStreamSynchronize(s));
-    out = g->hst[0];
+        return -1;
+    };
+    chunk_loop(c, g, 2, maxit, hist == nullptr, iteration, stopped);
+    const CgState st = read_state<CgState>(c, g);
+    SolveResult r;
+    r.stop = st.stop;
+    r.iters = st.k;
+    r.replacements = st.replacements;
+    r.nb = st.nb;
+    r.rr = st.rr;
+    r.rr_true = st.rr_true;
+    return r;
 }
 
-static int status_of(const CgState& st)
+static SolveResult run_single(cg_ctx* c, cg_graphs* g, double tol, int maxit, double* hist)
 {
-    switch (st.stop) {
+    hipStream_t s = c->stream;
+    SrArgs a = g->sargs;
+    a.hist = hist;
+    {
+        void* args0[] = {&a};
+        launch(g->kern.sr_setup, g->G, g->bs, s, args0);
+        void* args1[] = {&a, &tol, &maxit};
+        launch(g->kern.sr_first, g->G, g->bs, s, args1);
+    }
+    auto iteration = [&](int P) {
+        void* args[] = {&a, &P};
+        launch(g->kern.sr_iter, g->G, g->bs, s, args);
+    };
+    auto stopped = [&]() -> int {
+        SrState st = read_state<SrState>(c, g);
+        if (st.stop == STOP_CHECK) {
+            int P = st.k_done & 1, replace = 1, report = 0;
+            void* args[] = {&a, &P, &replace};
+            launch(g->kern.sr_residual, g->G, g->bs, s, args);
+            void* dargs[] = {&a, &report};
+            launch(g->kern.sr_decide, 1, g->bs, s, dargs);
+            st = read_state<SrState>(c, g);
+            if (st.stop == RUNNING) {  // replaced residual: w = A M^-1 r, then resume
+                void* rargs[] = {&a, &P};
+                launch(g->kern.sr_restart, g->G, g->bs, s, rargs);
+                return st.k_done + 1;
+            }
+        }
+        if (st.stop == STOP_MAXIT || st.stop == STOP_BREAKDOWN) {
+            int P = 0, replace = 0, report = 1;
+            void* args[] = {&a, &P, &replace};
+            launch(g->kern.sr_residual, g->G, g->bs, s, args);
+            void* dargs[] = {&a, &report};
+            launch(g->kern.sr_decide, 1, g->bs, s, dargs);
+        }
+        return -1;
+    };
+    chunk_loop(c, g, 1, maxit, hist == nullptr, iteration, stopped);
+    const SrState st = read_state<SrState>(c, g);
+    SolveResult r;
+    r.stop = st.stop;
+    r.iters = st.k_done;
+    r.replacements = st.replacements;
+    r.nb = st.nb;
+    r.rr = st.rr;
+    r.rr_true = st.rr_true;
+    return r;
+}
+
+// One FP64 solve through the graph path.  b, x are caller device pointers.
+static SolveResult run_solve(cg_ctx* c, cg_graphs* g, const double* b, double* x, double tol, int maxit,
+                             double* hist)
+{
+    hipStream_t s = c->stream;
+    const size_t vb = sizeof(double) * c->n;
+    JPCG_HIP(hipMemcpyAsync(g->cb, b, vb, hipMemcpyDeviceToDevice, s));
+    JPCG_HIP(hipMemcpyAsync(g->cx, x, vb, hipMemcpyDeviceToDevice, s));
+    const SolveResult r = g->form == CG_FORM_SINGLE_REDUCTION
+                              ? run_single(c, g, tol, maxit, hist)
+                              : run_standard<double>(c, g, g->args, tol, maxit, hist, true);
+    JPCG_HIP(hipMemcpyAsync(x, g->cx, vb, hipMemcpyDeviceToDevice, s));
+    JPCG_HIP(hipStreamSynchronize(s));
+    return r;
+}
+
+// Mixed precision: FP64 outer residual, scaling, refinement update and final
+// test; FP32 inner Jacobi-PCG on the FP32 copy of A.
+struct MixedResult {
+    int status = CG_MAXIT;
+    int outer = 0;
+    int inner_iters = 0;
+    double nb = 0.0, rr = 0.0;
+};
+
+static MixedResult run_mixed(cg_ctx* c, const double* b, double* x, double tol, int max_outer, double tol_in,
+                             int maxit_in)
+{
+    hipStream_t s = c->stream;
+    cg_graphs* g64 = c->graphs_std;
+    cg_graphs* g32 = c->graphs32;
+    const size_t vb = sizeof(double) * c->n;
+    JPCG_HIP(hipMemcpyAsync(g64->cb, b, vb, hipMemcpyDeviceToDevice, s));
+    JPCG_HIP(hipMemcpyAsync(g64->cx, x, vb, hipMemcpyDeviceToDevice, s));
+    CgArgsT<double> a64 = g64->args;
+    MixedResult res;
+    MixedState* hms = (MixedState*)c->mixed_host;
+    const int eg = std::min(4096, (c->n + 255) / 256);
+    for (int outer = 0;; ++outer) {
+        void* args0[] = {&a64};
+        launch(g64->kern.setup, g64->G, g64->bs, s, args0);  // r = b - A x in FP64
+        int n = c->n;
+        void* sargs[] = {&n, &a64.s.r, &a64.part_setup, &a64.G, &g32->cb, &g32->cx, &c->mixed_dev};
+        launch((const void*)k_mixed_scale<256>, eg, 256, s, sargs);
+        JPCG_HIP(hipMemcpyAsync(hms, c->mixed_dev, sizeof(MixedState), hipMemcpyDeviceToHost, s));
+        JPCG_HIP(hipStreamSynchronize(s));
+        res.outer = outer;
+        res.nb = std::sqrt(hms->bb);
+        res.rr = hms->rr;
+        if (!(res.rr == res.rr) || !(hms->bb == hms->bb)) {  // NaN input
+            res.status = CG_BREAKDOWN;
+            break;
+        }
+        if (res.nb == 0.0 || std::sqrt(res.rr) <= tol * res.nb) {
+            res.status = CG_CONVERGED;
+            if (res.nb == 0.0) JPCG_HIP(hipMemsetAsync(g64->cx, 0, vb, s));
+            break;
+        }
+        if (outer >= max_outer) {
+            res.status = CG_MAXIT;
+            break;
+        }
+        const SolveResult in = run_standard<float>(c, g32, g32->args32, tol_in, maxit_in, nullptr, false);
+        res.inner_iters += in.iters;
+        void* uargs[] = {&n, &a64.s.x, &g32->cx, &c->mixed_dev};
+        launch((const void*)k_mixed_update<256>, eg, 256, s, uargs);
+    }
+    JPCG_HIP(hipMemcpyAsync(x, g64->cx, vb, hipMemcpyDeviceToDevice, s));
+    JPCG_HIP(hipStreamSynchronize(s));
+    return res;
+}
+
+static int status_of(int stop)
+{
+    switch (stop) {
         case STOP_ZERO_RHS:
         case STOP_CONV0:
         case STOP_CONVERGED: return CG_CONVERGED;
@@ -688,12 +648,11 @@ static void autotune(cg_ctx* c)
             const int G = default_grid(c, sh[0], sh[1], bpc);
             cg_graphs* g = nullptr;
             try {
-                g = make_graphs(c, sh[0], sh[1], G, c->chunk);
-                CgState st;
+                g = make_graphs(c, c->form, false, sh[0], sh[1], G, c->chunk);
                 JPCG_HIP(hipMemsetAsync(xb, 0, sizeof(double) * c->n, c->stream));
-                run_solve(c, g, yb, xb, 0.0, 4, nullptr, st);  // warm
+                run_solve(c, g, yb, xb, 0.0, 4, nullptr);  // warm
                 JPCG_HIP(hipEventRecord(e0, c->stream));
-                run_solve(c, g, yb, xb, 0.0, iters, nullptr, st);
+                run_solve(c, g, yb, xb, 0.0, iters, nullptr);
                 JPCG_HIP(hipEventRecord(e1, c->stream));
                 JPCG_HIP(hipEventSynchronize(e1));
                 JPCG_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -738,8 +697,13 @@ static void autotune(cg_ctx* c)
 static void free_ctx(cg_ctx* c)
 {
     if (!c) return;
+    if (c->graphs_std != c->graphs) destroy_graphs(c->graphs_std);
     destroy_graphs(c->graphs);
-    void* ptrs[] = {c->rowptr, c->col, c->val, c->dinv, c->val32, c->dinv32, c->r, c->z, c->p0, c->p1, c->q, c->hist};
+    destroy_graphs(c->graphs32);
+    free_multi(c);
+    if (c->mixed_dev) (void)hipFree(c->mixed_dev);
+    if (c->mixed_host) (void)hipHostFree(c->mixed_host);
+    void* ptrs[] = {c->rowptr, c->col, c->val, c->dinv, c->val32, c->dinv32, c->rowsum32, c->work[0], c->hist};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -792,7 +756,8 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
         if (c->opts.precond == CG_PRECOND_DEFAULT) c->opts.precond = CG_PRECOND_JACOBI;
         if ((c->opts.precond != CG_PRECOND_JACOBI && c->opts.precond != CG_PRECOND_NONE) ||
             (c->opts.nnz_per_lane && !valid_npl(c->opts.nnz_per_lane)) ||
-            (c->opts.block_size && !valid_bs(c->opts.block_size)) || c->opts.chunk < 0 || c->opts.blocks_per_cu < 0) {
+            (c->opts.block_size && !valid_bs(c->opts.block_size)) || c->opts.chunk < 0 || c->opts.blocks_per_cu < 0 ||
+            (c->opts.form != CG_FORM_STANDARD && c->opts.form != CG_FORM_SINGLE_REDUCTION)) {
             free_ctx(c);
             return CG_EINVAL;
         }
@@ -833,7 +798,9 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
         JPCG_HIP(hipMalloc(&c->col, sizeof(int) * std::max<int64_t>(nnz, 1)));
         JPCG_HIP(hipMalloc(&c->val, sizeof(double) * std::max<int64_t>(nnz, 1)));
         JPCG_HIP(hipMalloc(&c->dinv, sizeof(double) * n));
-        for (double** v : {&c->r, &c->z, &c->p0, &c->p1, &c->q}) JPCG_HIP(hipMalloc(v, sizeof(double) * n));
+        JPCG_HIP(hipMalloc(&c->work[0], sizeof(double) * (size_t)n * cg_ctx::kWorkVecs));
+        for (int v = 1; v < cg_ctx::kWorkVecs; ++v) c->work[v] = c->work[0] + (size_t)v * n;
+        JPCG_HIP(hipMemsetAsync(c->work[0], 0, sizeof(double) * (size_t)n * cg_ctx::kWorkVecs, c->stream));
         JPCG_HIP(hipEventCreate(&c->ev0));
         JPCG_HIP(hipEventCreate(&c->ev1));
         JPCG_HIP(hipMemcpyAsync(c->rowptr, rp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, c->stream));
@@ -844,7 +811,9 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
         if (c->opts.fp32_copy) {
             JPCG_HIP(hipMalloc(&c->val32, sizeof(float) * std::max<int64_t>(nnz, 1)));
             JPCG_HIP(hipMalloc(&c->dinv32, sizeof(float) * n));
+            JPCG_HIP(hipMalloc(&c->rowsum32, sizeof(float) * n));
             if (nnz) cast_f32_kernel<<<1024, 256, 0, c->stream>>>(nnz, c->val, c->val32);
+            rowsum_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(n, c->rowptr, c->val, c->rowsum32);
             JPCG_HIP(hipGetLastError());
         }
         int* bad = nullptr;
@@ -865,6 +834,7 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
 
         // Launch shape: defaults, explicit options, or the autotuner.
         c->chunk = c->opts.chunk ? c->opts.chunk : 16;
+        c->form = c->opts.form;
         c->npl = c->opts.nnz_per_lane ? c->opts.nnz_per_lane : 8;
         c->bs = c->opts.block_size ? c->opts.block_size : 512;
         if (c->npl == 16 && c->bs == 1024) c->bs = 512;  // product tiles must fit 64 KiB of LDS
@@ -872,7 +842,17 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
         if (c->opts.autotune) {
             autotune(c);
         } else {
-            c->graphs = make_graphs(c, c->npl, c->bs, c->grid, c->chunk);
+            c->graphs = make_graphs(c, c->form, false, c->npl, c->bs, c->grid, c->chunk);
+        }
+        // The mixed form needs the standard FP64 graphs (outer residual) and
+        // FP32 standard graphs (inner solve) with the same tile shape.
+        if (c->opts.fp32_copy) {
+            c->graphs_std = c->form == CG_FORM_STANDARD
+                                ? c->graphs
+                                : make_graphs(c, CG_FORM_STANDARD, false, c->npl, c->bs, c->grid, c->chunk);
+            c->graphs32 = make_graphs(c, CG_FORM_STANDARD, true, c->npl, c->bs, c->grid, c->chunk);
+            JPCG_HIP(hipMalloc(&c->mixed_dev, 64));
+            JPCG_HIP(hipHostMalloc(&c->mixed_host, 64, hipHostMallocDefault));
         }
         *out = c;
         return 0;
@@ -909,17 +889,16 @@ int cg_solve(cg_ctx* c, const double* b, double* x, double tol, int32_t maxit, c
             }
             hist = c->hist;
         }
-        CgState st;
         JPCG_HIP(hipEventRecord(c->ev0, c->stream));
-        run_solve(c, c->graphs, b, x, tol, maxit, hist, st);
+        const SolveResult st = run_solve(c, c->graphs, b, x, tol, maxit, hist);
         JPCG_HIP(hipEventRecord(c->ev1, c->stream));
         JPCG_HIP(hipEventSynchronize(c->ev1));
         float ms = 0.f;
         JPCG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-        const int status = status_of(st);
-        c->hist_len = hist ? st.k + 1 : 0;
+        const int status = status_of(st.stop);
+        c->hist_len = hist ? st.iters + 1 : 0;
         if (info) {
-            info->iters = st.k;
+            info->iters = st.iters;
             info->status = status;
             info->replacements = st.replacements;
             info->outer = 0;
@@ -930,6 +909,39 @@ int cg_solve(cg_ctx* c, const double* b, double* x, double tol, int32_t maxit, c
         return status;
     } catch (const HipError& e) {
         return set_error(c, CG_EHIP, std::string("cg_solve: ") + e.what + ": " + hipGetErrorString(e.code));
+    }
+}
+
+int cg_solve_mixed(cg_ctx* c, const double* b, double* x, double tol, int32_t maxit_outer, double tol_inner,
+                   int32_t maxit_inner, cg_info* info)
+{
+    if (!c) return CG_EINVAL;
+    if (!c->graphs32) return set_error(c, CG_EINVAL, "cg_solve_mixed: the context was created without fp32_copy");
+    if (!b || !x || b == x || !(tol >= 0.0) || !std::isfinite(tol) || !(tol_inner >= 0.0) || !std::isfinite(tol_inner))
+        return set_error(c, CG_EINVAL, "cg_solve_mixed: bad arguments");
+    if (maxit_outer <= 0) maxit_outer = 50;
+    if (maxit_inner <= 0) maxit_inner = c->n;
+    if (tol_inner == 0.0) tol_inner = 1e-5;
+    try {
+        JPCG_HIP(hipEventRecord(c->ev0, c->stream));
+        const MixedResult r = run_mixed(c, b, x, tol, maxit_outer, tol_inner, maxit_inner);
+        JPCG_HIP(hipEventRecord(c->ev1, c->stream));
+        JPCG_HIP(hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        JPCG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        if (info) {
+            info->iters = r.inner_iters;
+            info->status = r.status;
+            info->replacements = 0;
+            info->outer = r.outer;
+            const double rel = r.nb > 0 ? std::sqrt(r.rr) / r.nb : 0.0;
+            info->relres_recur = rel;
+            info->relres_true = rel;
+            info->seconds = ms * 1e-3;
+        }
+        return r.status;
+    } catch (const HipError& e) {
+        return set_error(c, CG_EHIP, std::string("cg_solve_mixed: ") + e.what + ": " + hipGetErrorString(e.code));
     }
 }
 
@@ -964,8 +976,9 @@ int cg_get_config(cg_ctx* c, cg_config* cfg)
     cfg->nnz_per_lane = c->npl;
     cfg->block_size = c->bs;
     cfg->grid = c->grid;
-    cfg->tiles = c->graphs ? c->graphs->gb.T : 0;
+    cfg->tiles = c->graphs ? c->graphs->T : 0;
     cfg->chunk = c->chunk;
+    cfg->form = c->form;
     cfg->spmv_us = c->tuned_spmv_us;
     cfg->iter_us = c->tuned_iter_us;
     return 0;

@@ -33,6 +33,17 @@ enum : int {
     NSLOT = 8
 };
 
+// Stop codes of the graph-chunked solvers' device state.
+enum StopCode : int {
+    RUNNING = 0,
+    STOP_ZERO_RHS = 1,   // ||b|| = 0: x = 0
+    STOP_CONV0 = 2,      // x0 already satisfies the test
+    STOP_CHECK = 3,      // recurrence residual passed: confirm on b - A x
+    STOP_MAXIT = 4,
+    STOP_BREAKDOWN = 5,
+    STOP_CONVERGED = 6,  // confirmed
+};
+
 // Device-side result of a solve, copied back by the host.
 struct DevInfo {
     int iters;

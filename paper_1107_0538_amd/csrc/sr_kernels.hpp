@@ -1,0 +1,303 @@
+// Single-reduction Jacobi-PCG (the Chronopoulos-Gear form of the same
+// iteration): one kernel per iteration.
+//
+// Iteration k (the oracle's single-reduction loop, same symbols):
+//   sigma_k = delta_{k-1} - beta_{k-1} gamma_{k-1} / alpha_{k-1}, alpha_k = gamma_{k-1} / sigma_k
+//   p_{k-1} = u_{k-1} + beta_{k-1} p_{k-2},   s_{k-1} = w_{k-1} + beta_{k-1} s_{k-2}
+//   x_k = x_{k-1} + alpha_k p_{k-1},          r_k = r_{k-1} - alpha_k s_{k-1},  u_k = M^-1 r_k
+//   w_k = A u_k;  gamma_k = r_k'u_k, delta_k = w_k'u_k, ||r_k||^2   (one reduction)
+// Kernel K_k reduces the previous kernel's partials of (gamma, delta, r'r)
+// in its prologue, applies the continue-condition to r_{k-1}, and forms every
+// gathered u_k(j) on the fly from r_{k-1}, w_{k-1}, s_{k-2} and M^-1 of column
+// j with exactly the expressions the owning row lane uses, so w_k = A u_k
+// for the u_k that the row lanes store implicitly.  The gathered vectors r, w
+// and s alternate between two buffers by iteration parity; p and x update in
+// place (no other row reads them).
+#pragma once
+
+#include "tiles.hpp"
+
+namespace jpcg {
+
+struct SrState {
+    int stop;
+    int kk[2];   // kk[P] = iterations done after the kernel of parity P
+    int k_done;  // iterations done when a kernel raised the stop flag
+    int maxit;
+    int replacements;
+    double nb, thr;
+    double gam[2];    // gam[P] = gamma_{k-1}, written by K_k (P = k % 2)
+    double alpha[2];  // alpha[P] = alpha_k, written by K_k
+    double rr;        // ||r||^2 at the last continue-condition test
+    double rr_true;   // ||b - A x||^2 of the returned x
+};
+
+struct SrArgs {
+    int n;
+    const int* __restrict__ rowptr;
+    const int* __restrict__ col;
+    const double* __restrict__ val;
+    const double* __restrict__ dinv;
+    const double* b;
+    double* x;
+    double* R[2];
+    double* W[2];
+    double* S[2];
+    double* p;
+    TileMap tm;
+    int G;
+    double* part[2];     // [G][3]: gamma, delta, r'r from the kernel of parity P
+    double* part_setup;  // [G][2]: r'r, b'b of r0
+    double* part_chk;    // [G][1]: ||b - A x||^2 (check and report)
+    SrState* st;
+    double* hist;
+};
+
+template <int NPL, int BS>
+struct SrLds {
+    double red[(BS / kWave) * 4];
+    double prod[BS * NPL];
+};
+
+__device__ __forceinline__ int sr_logical(const SrArgs& a) { return xcd_logical_block((int)blockIdx.x, a.G); }
+__device__ __forceinline__ bool sr_leader(const SrArgs& a) { return threadIdx.x == 0 && sr_logical(a) == 0; }
+
+struct Quad {
+    double r, w, s, d;
+};
+struct Six {
+    double r, w, s, d, p, x;
+};
+
+// r0 = b - A x0 into R[0]; clears p and S[0] (read with a zero beta on the
+// first iteration); partials of r'r and b'b.
+template <int NPL, int BS>
+__global__ __launch_bounds__(BS) void k_sr_setup(SrArgs a)
+{
+    __shared__ SrLds<NPL, BS> sh;
+    double v[2] = {0.0, 0.0};
+    const double* __restrict__ x = a.x;
+    tile_rows<NPL, double>(
+        a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
+        [&](int j) { return x[j]; }, Ident<double>{}, [&](int i) { return a.b[i]; },
+        [&](int i, double ax, double bi) {
+            const double ri = bi - ax;
+            a.R[0][i] = ri;
+            a.p[i] = 0.0;
+            a.S[0][i] = 0.0;
+            v[0] += ri * ri;
+            v[1] += bi * bi;
+        },
+        NoPrologue{});
+    block_partials<BS, 2>(v, sh.red, a.part_setup, sr_logical(a));
+}
+
+// Initial tests, then w0 = A u0 into W[0] with the partials of (gamma0,
+// delta0, ||r0||^2) in part[0].
+template <int NPL, int BS>
+__global__ __launch_bounds__(BS) void k_sr_first(SrArgs a, double tol, int maxit)
+{
+    __shared__ SrLds<NPL, BS> sh;
+    double g[2];
+    wave_grid_sum<2>(a.part_setup, a.G, g);
+    const double rr = g[0], nb = sqrt(g[1]), thr = tol * nb;
+    SrState* st = a.st;
+    if (sr_leader(a)) {
+        st->kk[0] = 0;
+        st->kk[1] = 0;
+        st->k_done = 0;
+        st->maxit = maxit;
+        st->replacements = 0;
+        st->nb = nb;
+        st->thr = thr;
+        st->rr = rr;
+        st->rr_true = -1.0;
+        if (a.hist) a.hist[0] = nb > 0.0 ? sqrt(rr) / nb : 0.0;
+        st->stop = nb == 0.0 ? STOP_ZERO_RHS : (sqrt(rr) <= thr ? STOP_CONV0 : RUNNING);
+        if (nb == 0.0) st->rr_true = 0.0;
+        else if (sqrt(rr) <= thr) st->rr_true = rr;
+    }
+    if (nb == 0.0) {
+        // x = 0 over this workgroup's tile rows.
+        const int tb = sr_logical(a) * a.tm.per_block, t1 = min(tb + a.tm.per_block, a.tm.T);
+        if (tb < t1) {
+            const int rs = a.tm.tiles[tb].x, re = a.tm.tiles[t1 - 1].y;
+            for (int i = rs + (int)threadIdx.x; i < re; i += BS) a.x[i] = 0.0;
+        }
+        return;
+    }
+    if (sqrt(rr) <= thr) return;
+    const double* __restrict__ r0 = a.R[0];
+    const double* __restrict__ dinv = a.dinv;
+    double v[3] = {0.0, 0.0, 0.0};
+    tile_rows<NPL, double>(
+        a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
+        [&](int j) { return Pair2{r0[j], dinv[j]}; }, [&](Pair2 rd) { return rd.b * rd.a; },
+        [&](int i) { return Pair2{r0[i], dinv[i]}; },
+        [&](int i, double wi, Pair2 rd) {
+            const double ui = rd.b * rd.a;
+            a.W[0][i] = wi;
+            v[0] += rd.a * ui;
+            v[1] += wi * ui;
+            v[2] += rd.a * rd.a;
+        },
+        NoPrologue{});
+    block_partials<BS, 3>(v, sh.red, a.part[0], sr_logical(a));
+}
+
+// K_k, parity P = k % 2.
+template <int NPL, int BS>
+__global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
+{
+    __shared__ SrLds<NPL, BS> sh;
+    SrState* st = a.st;
+    const int Q = P ^ 1;
+    const double* __restrict__ rold = a.R[Q];
+    const double* __restrict__ wold = a.W[Q];
+    const double* __restrict__ sold = a.S[Q];
+    const double* __restrict__ dinv = a.dinv;
+    double* __restrict__ rnew = a.R[P];
+    double* __restrict__ wnew = a.W[P];
+    double* __restrict__ snew = a.S[P];
+    const bool lead = sr_leader(a);
+    double alpha = 0.0, beta = 0.0, gam_prev = 0.0;
+    int km1 = 0;
+    bool go = false;
+    auto prologue = [&]() -> bool {
+        const int stop = st->stop, maxit = st->maxit;
+        km1 = st->kk[Q];
+        const double thr = st->thr, nb = st->nb, gam2 = st->gam[Q], alpha1 = st->alpha[Q];
+        double g[3];
+        wave_grid_sum<3>(a.part[Q], a.G, g);
+        const double gam = g[0], delta = g[1], rr = g[2];
+        if (stop != RUNNING) return false;
+        if (lead) {
+            st->rr = rr;
+            if (a.hist) a.hist[km1] = sqrt(rr) / nb;
+        }
+        // The oracle's order: continue-condition, breakdown of gamma, iteration
+        // limit, then breakdown of sigma at the top of the next iteration.
+        int code = RUNNING;
+        double sigma = delta;
+        if (sqrt(rr) <= thr) code = STOP_CHECK;
+        else if (!(gam > 0.0) || !isfinite(gam)) code = STOP_BREAKDOWN;
+        else if (km1 >= maxit) code = STOP_MAXIT;
+        else {
+            if (km1 > 0) {
+                beta = gam / gam2;
+                sigma = delta - beta * gam / alpha1;
+            }
+            if (!(sigma > 0.0) || !isfinite(sigma)) code = STOP_BREAKDOWN;
+        }
+        if (code != RUNNING) {
+            if (lead) {
+                st->k_done = km1;
+                st->stop = code;
+            }
+            return false;
+        }
+        alpha = gam / sigma;
+        gam_prev = gam;
+        go = true;
+        return true;
+    };
+    double v[3] = {0.0, 0.0, 0.0};
+    tile_rows<NPL, double>(
+        a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
+        [&](int j) { return Quad{rold[j], wold[j], sold[j], dinv[j]}; },
+        [&](Quad q) {
+            const double s1 = __builtin_fma(beta, q.s, q.w);
+            return q.d * __builtin_fma(-alpha, s1, q.r);
+        },
+        [&](int i) { return Six{rold[i], wold[i], sold[i], dinv[i], a.p[i], a.x[i]}; },
+        [&](int i, double wi, Six o) {
+            const double u0 = o.d * o.r;
+            const double pi = __builtin_fma(beta, o.p, u0);
+            const double si = __builtin_fma(beta, o.s, o.w);
+            const double ri = __builtin_fma(-alpha, si, o.r);
+            const double ui = o.d * ri;
+            a.p[i] = pi;
+            snew[i] = si;
+            a.x[i] = __builtin_fma(alpha, pi, o.x);
+            rnew[i] = ri;
+            wnew[i] = wi;
+            v[0] += ri * ui;
+            v[1] += wi * ui;
+            v[2] += ri * ri;
+        },
+        prologue);
+    if (!go) return;  // the same decision in every wave of every workgroup
+    block_partials<BS, 3>(v, sh.red, a.part[P], sr_logical(a));
+    if (lead) {
+        st->kk[P] = km1 + 1;
+        st->gam[P] = gam_prev;
+        st->alpha[P] = alpha;
+    }
+}
+
+// ||b - A x||^2 into part_chk; if rout, the true residual replaces R[P] there.
+template <int NPL, int BS>
+__global__ __launch_bounds__(BS) void k_sr_residual(SrArgs a, int P, int replace)
+{
+    __shared__ SrLds<NPL, BS> sh;
+    double v[1] = {0.0};
+    const double* __restrict__ x = a.x;
+    double* __restrict__ rout = a.R[P];
+    tile_rows<NPL, double>(
+        a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
+        [&](int j) { return x[j]; }, Ident<double>{}, [&](int i) { return a.b[i]; },
+        [&](int i, double ax, double bi) {
+            const double ri = bi - ax;
+            if (replace) rout[i] = ri;
+            v[0] += ri * ri;
+        },
+        NoPrologue{});
+    block_partials<BS, 1>(v, sh.red, a.part_chk, sr_logical(a));
+}
+
+// One workgroup: accept (CONVERGED) or resume after replacement; with
+// report != 0 only record ||b - A x||^2.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_sr_decide(SrArgs a, int report)
+{
+    double g[1];
+    wave_grid_sum<1>(a.part_chk, a.G, g);
+    if (threadIdx.x == 0) {
+        SrState* st = a.st;
+        if (report) {
+            st->rr_true = g[0];
+        } else if (sqrt(g[0]) <= st->thr) {
+            st->stop = STOP_CONVERGED;
+            st->rr_true = g[0];
+        } else {
+            st->stop = RUNNING;
+            st->replacements += 1;
+        }
+    }
+}
+
+// After a replacement: w = A M^-1 r for the replaced r in R[P], with the
+// partials of (gamma, delta, r'r) in part[P] for the next iteration.
+template <int NPL, int BS>
+__global__ __launch_bounds__(BS) void k_sr_restart(SrArgs a, int P)
+{
+    __shared__ SrLds<NPL, BS> sh;
+    const double* __restrict__ r = a.R[P];
+    const double* __restrict__ dinv = a.dinv;
+    double v[3] = {0.0, 0.0, 0.0};
+    tile_rows<NPL, double>(
+        a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
+        [&](int j) { return Pair2{r[j], dinv[j]}; }, [&](Pair2 rd) { return rd.b * rd.a; },
+        [&](int i) { return Pair2{r[i], dinv[i]}; },
+        [&](int i, double wi, Pair2 rd) {
+            const double ui = rd.b * rd.a;
+            a.W[P][i] = wi;
+            v[0] += rd.a * ui;
+            v[1] += wi * ui;
+            v[2] += rd.a * rd.a;
+        },
+        NoPrologue{});
+    block_partials<BS, 3>(v, sh.red, a.part[P], sr_logical(a));
+}
+
+}  // namespace jpcg

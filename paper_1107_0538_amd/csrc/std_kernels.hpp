@@ -1,0 +1,354 @@
+// Standard-form Jacobi-PCG kernels (two per iteration), templated on the
+// value type T of the matrix and vectors: double for the FP64 solve, float
+// for the inner solve of the mixed-precision form.  Dot products, partial
+// sums and every scalar (alpha, beta, the tests) stay in double.
+//
+//   A_k  (k_direction)  reduce the previous B's partials of r'z and r'r, apply
+//        the continue-condition / breakdown / iteration-limit tests,
+//        beta_k = rho_{k-1} / rho_{k-2}; p_k = z + beta_k p_{k-1} formed inside
+//        the gather of q = A p_k; partials of p_k' q.
+//   B_k  (k_update)  reduce A_k's partials, alpha_k = rho_{k-1} / sigma_k;
+//        x += alpha p, r -= alpha q, z = M^-1 r; partials of r'z and r'r.
+//
+// Every workgroup reduces the previous kernel's per-workgroup partials itself,
+// in a fixed order, so all workgroups reach the same bits and the same
+// decision without atomics.  Scalars that must outlive a kernel sit in a small
+// state block, double-buffered by iteration parity so that no kernel reads a
+// slot it writes.
+#pragma once
+
+#include "phases.hpp"
+#include "tiles.hpp"
+
+namespace jpcg {
+
+struct CgState {
+    int stop;
+    int k;  // completed iterations (advanced by B's workgroup 0)
+    int maxit;
+    int replacements;
+    double nb;       // ||b||
+    double thr;      // tol * ||b||
+    double rho[2];   // rho[k % 2] = r_{k-1}' z_{k-1}, written by A_k
+    double rr;       // ||r_k||^2 seen by the last continue-condition test
+    double rr_true;  // ||b - A x||^2 of the returned x
+    double sigma, alpha, beta;
+};
+
+template <typename T>
+struct CgArgsT {
+    SysView<T> s;  // b, x are the solver's own buffers; p0/p1 alternate by parity
+    const T* rowsum;  // FP32 solves: row sums of A (computed in FP64) for the row-sum-preserving product
+    TileMap tm;    // tiles of the sparse products, per workgroup
+    int R;         // rows per workgroup of the elementwise update
+    int G;
+    double* part_setup;    // [G][3]: r'r, r'z, b'b of r0
+    double* part_sig;      // [G][1]: p'q
+    double* part_iter[2];  // [G][2]: r'z, r'r after B of parity P (or a check)
+    double* part_rep;      // [G][1]: ||b - A x||^2 for the report
+    CgState* st;
+    double* hist;
+};
+
+// FP32 products use the row-sum-preserving evaluation (see tiles.hpp): the
+// FP32 copy of A alone would misrepresent the near-constant modes that
+// dominate x for these Neumann-plus-mass systems.
+template <typename T>
+constexpr bool kDiff = sizeof(T) == 4;
+
+template <int NPL, int BS, typename T>
+struct Lds {
+    double red[(BS / kWave) * 4];
+    T prod[BS * NPL * (kDiff<T> ? 2 : 1)];  // per wave: 64 * NPL products (values and entries when DIFF)
+};
+
+template <int NPL, typename T>
+__device__ __forceinline__ T* wave_prod(T* prod)
+{
+    return prod + (threadIdx.x / kWave) * (kWave * NPL * (kDiff<T> ? 2 : 1));
+}
+
+// The tile walk in the evaluation that suits T.
+template <int NPL, typename T, typename Gather, typename Value, typename Pre, typename Self, typename Row,
+          typename Prologue>
+__device__ __forceinline__ void walk(const SysView<T>& s, const T* rowsum, const TileMap& tm, int L, T* prod,
+                                     Gather gather, Value value, Pre pre, Self self, Row row, Prologue prologue)
+{
+    tile_rows_x<NPL, T, kDiff<T>>(s.rowptr, s.col, s.val, rowsum, tm, L, wave_prod<NPL>(prod), gather, value, pre,
+                                  self, row, prologue);
+}
+
+template <typename T>
+struct Tri {
+    T a, b, c;
+};
+
+__device__ __forceinline__ int logical_of(int G) { return xcd_logical_block((int)blockIdx.x, G); }
+
+template <typename T>
+struct PairT {
+    T a, b;
+};
+
+// r_out = b - A x and (if z_out) z_out = M^-1 r_out over the workgroup's tiles;
+// shares of r'r, r'z, b'b.
+template <int NPL, int BS, typename T>
+__device__ __forceinline__ void tile_residual(const CgArgsT<T>& a, T* prod, T* r_out, T* z_out, double& rr,
+                                              double& rz, double& bb)
+{
+    const SysView<T>& s = a.s;
+    const T* __restrict__ x = s.x;
+    walk<NPL, T>(
+        s, a.rowsum, a.tm, logical_of(a.G), prod, [&](int j) { return x[j]; }, Ident<T>{},
+        [&](int i) { return Tri<T>{s.b[i], s.dinv[i], kDiff<T> ? x[i] : T(0)}; }, [&](const Tri<T>& t) { return t.c; },
+        [&](int i, T ax, Tri<T> bd) {
+            const T bi = bd.a;
+            const T ri = bi - ax;
+            r_out[i] = ri;
+            rr += (double)ri * (double)ri;
+            bb += (double)bi * (double)bi;
+            if (z_out) {
+                const T zi = bd.b * ri;
+                z_out[i] = zi;
+                rz += (double)ri * (double)zi;
+            }
+        },
+        NoPrologue{});
+}
+
+template <int NPL, int BS, typename T>
+__global__ __launch_bounds__(BS) void k_setup(CgArgsT<T> a)
+{
+    __shared__ Lds<NPL, BS, T> sh;
+    double v[3] = {0.0, 0.0, 0.0};
+    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.s.z, v[0], v[1], v[2]);
+    block_partials<BS, 3>(v, sh.red, a.part_setup, logical_of(a.G));
+}
+
+// A_1: initial tests, then p_1 = z_0, q = A p_1.
+template <int NPL, int BS, typename T>
+__global__ __launch_bounds__(BS) void k_first(CgArgsT<T> a, double tol, int maxit)
+{
+    __shared__ Lds<NPL, BS, T> sh;
+    double g[3];
+    wave_grid_sum<3>(a.part_setup, a.G, g);
+    const double rr = g[0], rho = g[1], nb = sqrt(g[2]), thr = tol * nb;
+    CgState* st = a.st;
+    const SysView<T>& s = a.s;
+    const int L = logical_of(a.G);
+    if (threadIdx.x == 0 && L == 0) {
+        st->k = 0;
+        st->maxit = maxit;
+        st->replacements = 0;
+        st->nb = nb;
+        st->thr = thr;
+        st->rho[1] = rho;
+        st->rr = rr;
+        st->rr_true = -1.0;
+        if (a.hist) a.hist[0] = nb > 0.0 ? sqrt(rr) / nb : 0.0;
+        st->stop = nb == 0.0 ? STOP_ZERO_RHS : (sqrt(rr) <= thr ? STOP_CONV0 : RUNNING);
+        if (nb == 0.0) st->rr_true = 0.0;
+        else if (sqrt(rr) <= thr) st->rr_true = rr;
+    }
+    if (nb == 0.0) {
+        const int rs = min(L * a.R, s.n), re = min(rs + a.R, s.n);
+        for (int i = rs + (int)threadIdx.x; i < re; i += BS) s.x[i] = T(0);
+        return;
+    }
+    if (sqrt(rr) <= thr) return;
+    const T* __restrict__ z = s.z;
+    double sig = 0.0;
+    walk<NPL, T>(
+        s, a.rowsum, a.tm, L, sh.prod, [&](int j) { return z[j]; }, Ident<T>{}, [&](int i) { return z[i]; },
+        [&](T zi) { return zi; },
+        [&](int i, T qi, T pi) {
+            s.p1[i] = pi;
+            s.q[i] = qi;
+            sig += (double)pi * (double)qi;
+        },
+        NoPrologue{});
+    double v[1] = {sig};
+    block_partials<BS, 1>(v, sh.red, a.part_sig, L);
+}
+
+// A_k, k >= 2, parity P = k % 2.  The scalar work (reducing the previous B's
+// partials, the tests, beta) runs as the tile walk's prologue, after the
+// first gathers are issued, so its memory latency overlaps theirs.
+template <int NPL, int BS, typename T>
+__global__ __launch_bounds__(BS) void k_direction(CgArgsT<T> a, int P)
+{
+    __shared__ Lds<NPL, BS, T> sh;
+    CgState* st = a.st;
+    const SysView<T>& s = a.s;
+    const T* __restrict__ z = s.z;
+    const T* __restrict__ pold = P ? s.p0 : s.p1;
+    T* __restrict__ pnew = P ? s.p1 : s.p0;
+    const int L = logical_of(a.G);
+    const bool lead = threadIdx.x == 0 && L == 0;
+    T beta = T(0);
+    double sig = 0.0;
+    bool go = true;
+    auto prologue = [&]() -> bool {
+        const int stop = st->stop, km1 = st->k, maxit = st->maxit;
+        const double thr = st->thr, nb = st->nb, rho_prev = st->rho[P ^ 1];
+        double g[2];
+        wave_grid_sum<2>(a.part_iter[P ^ 1], a.G, g);
+        const double rz = g[0], rr = g[1];
+        go = false;
+        if (stop != RUNNING) return false;
+        if (lead) {
+            st->rr = rr;
+            if (a.hist) a.hist[km1] = sqrt(rr) / nb;
+        }
+        // The oracle's order: continue-condition, breakdown of r'z, iteration limit.
+        if (sqrt(rr) <= thr) {
+            if (lead) st->stop = STOP_CHECK;
+            return false;
+        }
+        if (!(rz > 0.0) || !isfinite(rz)) {
+            if (lead) st->stop = STOP_BREAKDOWN;
+            return false;
+        }
+        if (km1 >= maxit) {
+            if (lead) st->stop = STOP_MAXIT;
+            return false;
+        }
+        const double b = rz / rho_prev;
+        beta = (T)b;
+        if (lead) {
+            st->rho[P] = rz;
+            st->beta = b;
+        }
+        go = true;
+        return true;
+    };
+    walk<NPL, T>(
+        s, a.rowsum, a.tm, L, sh.prod, [&](int j) { return PairT<T>{z[j], pold[j]}; },
+        [&](PairT<T> zp) { return fma_t(beta, zp.b, zp.a); }, [&](int i) { return PairT<T>{z[i], pold[i]}; },
+        [&](PairT<T> zp) { return fma_t(beta, zp.b, zp.a); },
+        [&](int i, T qi, PairT<T> zp) {
+            const T pi = fma_t(beta, zp.b, zp.a);
+            pnew[i] = pi;
+            s.q[i] = qi;
+            sig += (double)pi * (double)qi;
+        },
+        prologue);
+    if (!go) return;  // the same decision in every wave of every workgroup
+    double v[1] = {sig};
+    block_partials<BS, 1>(v, sh.red, a.part_sig, L);
+}
+
+// B_k, parity P = k % 2.  Rows are split arithmetically; the state, the row
+// operands and the partials of sigma are all requested before any is used.
+template <int BS, typename T>
+__global__ __launch_bounds__(BS) void k_update(CgArgsT<T> a, int P)
+{
+    __shared__ Lds<1, BS, T> sh;
+    CgState* st = a.st;
+    const SysView<T>& s = a.s;
+    const int stop = st->stop;
+    const double rho = st->rho[P];
+    const int L = logical_of(a.G);
+    const int rs = min(L * a.R, s.n), re = min(rs + a.R, s.n);
+    const T* __restrict__ p = P ? s.p1 : s.p0;
+    const int i0 = rs + (int)threadIdx.x;
+    const bool h0 = i0 < re;
+    const int ic = h0 ? i0 : 0;
+    const T p0 = p[ic], q0 = s.q[ic], x0 = s.x[ic], r0 = s.r[ic], d0 = s.dinv[ic];
+    double g[1];
+    wave_grid_sum<1>(a.part_sig, a.G, g);
+    const double sigma = g[0];
+    if (stop != RUNNING) return;
+    const bool lead = threadIdx.x == 0 && L == 0;
+    if (!(sigma > 0.0) || !isfinite(sigma)) {
+        if (lead) st->stop = STOP_BREAKDOWN;
+        return;
+    }
+    const double alpha_d = rho / sigma;
+    const T alpha = (T)alpha_d;
+    double v[2] = {0.0, 0.0};
+    if (h0) {
+        s.x[i0] = fma_t(alpha, p0, x0);
+        const T ri = fma_t(-alpha, q0, r0);
+        s.r[i0] = ri;
+        const T zi = d0 * ri;
+        s.z[i0] = zi;
+        v[0] += (double)ri * (double)zi;
+        v[1] += (double)ri * (double)ri;
+    }
+    for (int i = i0 + BS; i < re; i += BS) {
+        s.x[i] = fma_t(alpha, p[i], s.x[i]);
+        const T ri = fma_t(-alpha, s.q[i], s.r[i]);
+        s.r[i] = ri;
+        const T zi = s.dinv[i] * ri;
+        s.z[i] = zi;
+        v[0] += (double)ri * (double)zi;
+        v[1] += (double)ri * (double)ri;
+    }
+    block_partials<BS, 2>(v, sh.red, a.part_iter[P], L);
+    if (lead) {
+        st->k = st->k + 1;
+        st->sigma = sigma;
+        st->alpha = alpha_d;
+    }
+}
+
+// True residual r = b - A x, z = M^-1 r into the slot the next A_{k+1} reads.
+template <int NPL, int BS, typename T>
+__global__ __launch_bounds__(BS) void k_check(CgArgsT<T> a, int P)
+{
+    __shared__ Lds<NPL, BS, T> sh;
+    double rr = 0.0, rz = 0.0, bb = 0.0;
+    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.s.z, rr, rz, bb);
+    double v[2] = {rz, rr};
+    block_partials<BS, 2>(v, sh.red, a.part_iter[P], logical_of(a.G));
+}
+
+// One workgroup: accept the solve, or resume with the replaced residual.
+template <int BS, typename T>
+__global__ __launch_bounds__(BS) void k_check_decide(CgArgsT<T> a, int P)
+{
+    double g[2];
+    wave_grid_sum<2>(a.part_iter[P], a.G, g);
+    if (threadIdx.x == 0) {
+        CgState* st = a.st;
+        if (sqrt(g[1]) <= st->thr) {
+            st->stop = STOP_CONVERGED;
+            st->rr_true = g[1];
+        } else {
+            st->stop = RUNNING;
+            st->replacements += 1;
+        }
+    }
+}
+
+// ||b - A x||^2 of the returned x, for solves that end without convergence.
+template <int NPL, int BS, typename T>
+__global__ __launch_bounds__(BS) void k_report(CgArgsT<T> a)
+{
+    __shared__ Lds<NPL, BS, T> sh;
+    double v[1] = {0.0};
+    double rz = 0.0, bb = 0.0;
+    tile_residual<NPL, BS, T>(a, sh.prod, a.s.q, (T*)nullptr, v[0], rz, bb);
+    block_partials<BS, 1>(v, sh.red, a.part_rep, logical_of(a.G));
+}
+
+template <int BS, typename T>
+__global__ __launch_bounds__(BS) void k_report_sum(CgArgsT<T> a)
+{
+    double g[1];
+    wave_grid_sum<1>(a.part_rep, a.G, g);
+    if (threadIdx.x == 0) a.st->rr_true = g[0];
+}
+
+// y = A x over the solver's tiles (rows summed in stored order).
+template <int NPL, int BS, typename T>
+__global__ __launch_bounds__(BS) void k_spmv(CgArgsT<T> a, const T* __restrict__ x, T* __restrict__ y)
+{
+    __shared__ Lds<NPL, BS, T> sh;
+    walk<NPL, T>(a.s, a.rowsum, a.tm, logical_of(a.G), sh.prod, [&](int j) { return x[j]; }, Ident<T>{},
+                 [&](int i) { return kDiff<T> ? x[i] : T(0); }, [&](T xi) { return xi; }, [&](int i, T v, T) { y[i] = v; },
+                 NoPrologue{});
+}
+
+}  // namespace jpcg

@@ -66,20 +66,29 @@ __device__ __forceinline__ T lds_row_sum(const T* prod, int a, int b)
 }
 
 // Visit every row of the workgroup's tiles.
-//   gather(j)        raw operand(s) of column j (type GV), loaded per nonzero
-//   combine(v, g)    the product a_ij * (vector entry) from value v and g
-//   pre(i)           raw operand(s) of row i for the row step (type PV)
-//   row(i, sum, pv)  consumes a finished row; one lane per row
-//   prologue()       runs once per wave after the wave's first gathers are
-//                    issued (or at the end if the wave has no tile); it may
-//                    load and reduce scalars that combine/row depend on, so
-//                    that latency overlaps the gathers.  Returning false ends
-//                    the wave's work.
-// `prod` is this wave's LDS slice of 64 * NPL values.
-template <int NPL, typename T, typename Gather, typename Combine, typename Pre, typename Row, typename Prologue>
-__device__ __forceinline__ void tile_rows(const int* __restrict__ rowptr, const int* __restrict__ col,
-                                          const T* __restrict__ val, const TileMap& tm, int L, T* prod,
-                                          Gather gather, Combine combine, Pre pre, Row row, Prologue prologue)
+//   gather(j)       raw operand(s) of column j (type GV), loaded per nonzero
+//   value(g)        the vector entry x_j from the raw operands (may use scalars
+//                   that the prologue sets)
+//   pre(i)          raw operand(s) of row i for the row step (type PV)
+//   row(i, y, pv)   consumes y_i = (A x)_i; called by one lane per row
+//   prologue()      runs once per wave after the wave's first gathers are
+//                   issued (or at the end if the wave has no tile); it may
+//                   load and reduce scalars that value/row depend on, so that
+//                   latency overlaps the gathers.  Returning false ends the
+//                   wave's work.
+// With DIFF the product is evaluated in row-sum-preserving form,
+//   y_i = sum_{j != i} a_ij (x_j - x_i) + s_i x_i,   s_i = sum_j a_ij,
+// with self(pv) giving the row's own x_i and rowsum[i] = s_i (computed in
+// double, stored in T).  A constant vector then costs no cancellation, which
+// keeps a float product accurate on the smooth near-null modes of a
+// Neumann-plus-mass operator.  `prod` is this wave's LDS slice of 64 * NPL
+// values (twice that with DIFF).
+template <int NPL, typename T, bool DIFF = false, typename Gather, typename Value, typename Pre, typename Self,
+          typename Row, typename Prologue>
+__device__ __forceinline__ void tile_rows_x(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                            const T* __restrict__ val, const T* __restrict__ rowsum,
+                                            const TileMap& tm, int L, T* prod, Gather gather, Value value, Pre pre,
+                                            Self self, Row row, Prologue prologue)
 {
     constexpr int CAP = kWave * NPL;
     using GV = decltype(gather(0));
@@ -88,6 +97,7 @@ __device__ __forceinline__ void tile_rows(const int* __restrict__ rowptr, const 
     const int nwaves = blockDim.x / kWave;
     const int tb = L * tm.per_block;
     const int t1 = min(tb + tm.per_block, tm.T);
+    T* px = prod + CAP;  // DIFF: gathered entries next to the values
     bool ready = false;
     for (int t = tb + wave; t < t1; t += nwaves) {
         const int4 d = tm.tiles[t];
@@ -123,14 +133,31 @@ __device__ __forceinline__ void tile_rows(const int* __restrict__ rowptr, const 
                 if (!prologue()) return;
                 ready = true;
             }
+            if constexpr (DIFF) {
 #pragma unroll
-            for (int j = 0; j < NPL; ++j) prod[lane + kWave * j] = combine(v[j], g[j]);
+                for (int j = 0; j < NPL; ++j) {
+                    prod[lane + kWave * j] = v[j];
+                    px[lane + kWave * j] = value(g[j]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < NPL; ++j) prod[lane + kWave * j] = v[j] * value(g[j]);
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (has_row) row(i0, lds_row_sum(prod, ra - k0, rb - k0), pv);
-            for (int i = i0 + kWave; i < r1; i += kWave)  // tiles of more than 64 rows
-                row(i, lds_row_sum(prod, rowptr[i] - k0, rowptr[i + 1] - k0), pre(i));
+            for (int i = i0; i < r1; i += kWave) {  // more than 64 rows only in tiny-row tiles
+                const auto pvi = i == i0 ? pv : pre(i);
+                const int a = (i == i0 ? ra : rowptr[i]) - k0, b = (i == i0 ? rb : rowptr[i + 1]) - k0;
+                if constexpr (DIFF) {
+                    const T xi = self(pvi);
+                    T s = T(0);
+                    for (int k = a; k < b; ++k) s += prod[k] * (px[k] - xi);
+                    row(i, s + rowsum[i] * xi, pvi);
+                } else {
+                    row(i, lds_row_sum(prod, a, b), pvi);
+                }
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -140,15 +167,41 @@ __device__ __forceinline__ void tile_rows(const int* __restrict__ rowptr, const 
                 if (!prologue()) return;
                 ready = true;
             }
+            const auto pvi = pre(r0);
             T acc = T(0);
-            for (int k = k0 + lane; k < k1; k += kWave) acc += combine(val[k], gather(col[k]));
+            if constexpr (DIFF) {
+                const T xi = self(pvi);
+                for (int k = k0 + lane; k < k1; k += kWave) acc += val[k] * (value(gather(col[k])) - xi);
+            } else {
+                for (int k = k0 + lane; k < k1; k += kWave) acc += val[k] * value(gather(col[k]));
+            }
 #pragma unroll
             for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-            if (lane == 0) row(r0, acc, pre(r0));
+            if constexpr (DIFF) acc += rowsum[r0] * self(pvi);
+            if (lane == 0) row(r0, acc, pvi);
         }
     }
     if (!ready) prologue();
 }
+
+struct NoSelf {
+    template <typename P>
+    __device__ __forceinline__ int operator()(const P&) const { return 0; }
+};
+
+// The plain (non-DIFF) walk.
+template <int NPL, typename T, typename Gather, typename Value, typename Pre, typename Row, typename Prologue>
+__device__ __forceinline__ void tile_rows(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                          const T* __restrict__ val, const TileMap& tm, int L, T* prod,
+                                          Gather gather, Value value, Pre pre, Row row, Prologue prologue)
+{
+    tile_rows_x<NPL, T, false>(rowptr, col, val, (const T*)nullptr, tm, L, prod, gather, value, pre, NoSelf{}, row,
+                               prologue);
+}
+
+struct Pair2 {
+    double a, b;
+};
 
 struct NoPre {
     __device__ __forceinline__ int operator()(int) const { return 0; }
@@ -159,8 +212,8 @@ struct NoPrologue {
 };
 
 template <typename T>
-struct Mul {
-    __device__ __forceinline__ T operator()(T v, T g) const { return v * g; }
+struct Ident {
+    __device__ __forceinline__ T operator()(T g) const { return g; }
 };
 
 }  // namespace jpcg

@@ -57,7 +57,7 @@ def make_csr(a) -> tuple[capi.cg_csr, list]:
 
 
 def make_opts(precond="jacobi", fp32_copy=False, autotune=False, nnz_per_lane=0, blocks_per_cu=0,
-              history=False, block_size=0, chunk=0) -> capi.cg_opts:
+              history=False, block_size=0, chunk=0, form="standard") -> capi.cg_opts:
     o = capi.cg_opts()
     capi.load().cg_opts_default(ctypes.byref(o))
     o.precond = {"jacobi": capi.CG_PRECOND_JACOBI, "none": capi.CG_PRECOND_NONE}[precond]
@@ -68,6 +68,7 @@ def make_opts(precond="jacobi", fp32_copy=False, autotune=False, nnz_per_lane=0,
     o.history = int(bool(history))
     o.block_size = int(block_size)
     o.chunk = int(chunk)
+    o.form = capi.FORMS[form]
     return o
 
 
@@ -75,14 +76,15 @@ class Solver:
     """A cg_ctx: one SPD CSR matrix resident on the GPU."""
 
     def __init__(self, a, precond="jacobi", fp32_copy=False, autotune=False, nnz_per_lane=0,
-                 blocks_per_cu=0, history=False, block_size=0, chunk=0, stream=None):
+                 blocks_per_cu=0, history=False, block_size=0, chunk=0, form="standard", stream=None):
         torch = _torch()
         self._lib = capi.load()
         self.n = int(a.n)
         self.nnz = int(a.rowptr[-1])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         csr, _keep = make_csr(a)
-        opts = make_opts(precond, fp32_copy, autotune, nnz_per_lane, blocks_per_cu, history, block_size, chunk)
+        opts = make_opts(precond, fp32_copy, autotune, nnz_per_lane, blocks_per_cu, history, block_size, chunk,
+                         form)
         ctx = ctypes.c_void_p()
         rc = self._lib.cg_create(ctypes.byref(csr), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(ctx))
@@ -123,6 +125,22 @@ class Solver:
         info = self.cg_solve(b, x, tol, maxit)
         return x, info
 
+    def cg_solve_mixed(self, b, x, tol=1e-10, maxit_outer=0, tol_inner=1e-5, maxit_inner=0) -> dict:
+        """In-place mixed-precision solve (FP32 inner CG, FP64 refinement)."""
+        _as_device_vec(b, self.n, "b")
+        _as_device_vec(x, self.n, "x")
+        info = capi.cg_info()
+        rc = self._lib.cg_solve_mixed(self.ctx, b.data_ptr(), x.data_ptr(), float(tol), int(maxit_outer),
+                                      float(tol_inner), int(maxit_inner), ctypes.byref(info))
+        capi.check(rc, self.ctx)
+        return info.as_dict()
+
+    def solve_mixed(self, b, x0=None, tol=1e-10, maxit_outer=0, tol_inner=1e-5, maxit_inner=0):
+        torch = _torch()
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        info = self.cg_solve_mixed(b, x, tol, maxit_outer, tol_inner, maxit_inner)
+        return x, info
+
     def spmv(self, x, y=None):
         torch = _torch()
         _as_device_vec(x, self.n, "x")
@@ -131,6 +149,38 @@ class Solver:
         _as_device_vec(y, self.n, "y")
         capi.check(self._lib.spmv(self.ctx, x.data_ptr(), y.data_ptr()), self.ctx)
         return y
+
+    # -- multi-RHS ------------------------------------------------------------------
+    def _as_block(self, t, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or t.dim() != 2 \
+                or t.shape[0] != self.n or not (1 <= t.shape[1] <= 64) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape (n, s), 1 <= s <= 64")
+        return t
+
+    def spmm(self, X, Y=None):
+        torch = _torch()
+        self._as_block(X, "X")
+        if Y is None:
+            Y = torch.empty_like(X)
+        self._as_block(Y, "Y")
+        capi.check(self._lib.spmm(self.ctx, X.data_ptr(), Y.data_ptr(), X.shape[1]), self.ctx)
+        return Y
+
+    def cg_solve_multi(self, B, X, tol=1e-10, maxit=0) -> list:
+        self._as_block(B, "B")
+        self._as_block(X, "X")
+        s = B.shape[1]
+        infos = (capi.cg_info * s)()
+        rc = self._lib.cg_solve_multi(self.ctx, B.data_ptr(), X.data_ptr(), s, float(tol), int(maxit), infos)
+        capi.check(rc, self.ctx)
+        return [infos[j].as_dict() for j in range(s)]
+
+    def solve_multi(self, B, X0=None, tol=1e-10, maxit=0):
+        torch = _torch()
+        X = torch.zeros_like(B) if X0 is None else X0.clone()
+        infos = self.cg_solve_multi(B, X, tol, maxit)
+        return X, infos
 
     # -- introspection -------------------------------------------------------------
     def history(self) -> np.ndarray:

@@ -1,0 +1,113 @@
+"""Multi-RHS form: s independent Jacobi-PCG recurrences sharing one product per iteration.
+
+Each column is judged against its own FP64 oracle solve with the single-RHS
+criteria (+-2 iterations, solution within 1e-8, true relres <= 1e-10); spmm's
+column j must equal the oracle's sequential product of column j bitwise.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def mat(n, seed=0):
+    return W.problem(n, seed)[0]
+
+
+def _t(a, dev):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev)
+
+
+@pytest.mark.parametrize("n,s", [(16, 64), (16, 7), (51, 64), (3, 1)])
+def test_spmm_bitwise(cuda, n, s):
+    from paper_1107_0538_amd import Solver
+
+    a = mat(n)
+    X = np.random.default_rng(n + s).uniform(-1, 1, (a.n, s))
+    Y = Solver(a).spmm(_t(X, cuda)).cpu().numpy()
+    for j in range(s):
+        assert np.array_equal(Y[:, j], oracle.spmv(a, X[:, j])), j
+
+
+@pytest.mark.parametrize("s", [64, 5])
+def test_multi_rhs_parity_16(cuda, s):
+    from paper_1107_0538_amd import Solver
+
+    a = mat(16)
+    B = W.multi_rhs(a.n, s)
+    X, infos = Solver(a).solve_multi(_t(B, cuda))
+    X = X.cpu().numpy()
+    for j in range(s):
+        xo, io = oracle.pcg(a, B[:, j])
+        assert infos[j]["status"] == 0 and io["status"] == 0
+        assert abs(infos[j]["iters"] - io["iters"]) <= 2, (j, infos[j], io)
+        assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) <= 1e-8
+        assert oracle.relres(a, B[:, j], X[:, j]) <= 1e-10
+
+
+def test_multi_rhs_51_sampled(cuda):
+    # The multi-RHS workload: 64 right-hand sides on the 51^3 matrix.
+    from paper_1107_0538_amd import Solver
+
+    a = mat(51)
+    B = W.multi_rhs(a.n, 64)
+    X, infos = Solver(a).solve_multi(_t(B, cuda))
+    X = X.cpu().numpy()
+    for j in range(64):
+        assert infos[j]["status"] == 0
+        assert oracle.relres(a, B[:, j], X[:, j]) <= 1e-10
+    for j in (0, 17, 63):
+        xo, io = oracle.pcg(a, B[:, j])
+        assert abs(infos[j]["iters"] - io["iters"]) <= 2
+        assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_multi_rhs_mixed_columns(cuda):
+    # Zero column, a column already solved by X0, a NaN column, and normal ones.
+    from paper_1107_0538_amd import Solver
+
+    a = mat(7)
+    rng = np.random.default_rng(9)
+    B = rng.uniform(-1, 1, (a.n, 6))
+    B[:, 1] = 0.0
+    xs, _ = oracle.pcg(a, B[:, 2], tol=1e-13)
+    X0 = np.zeros_like(B)
+    X0[:, 1] = 1.0
+    X0[:, 2] = xs
+    B[3, 4] = np.nan
+    X, infos = Solver(a).solve_multi(_t(B, cuda), X0=_t(X0, cuda))
+    X = X.cpu().numpy()
+    assert infos[1]["status"] == 0 and infos[1]["iters"] == 0 and not X[:, 1].any()
+    assert infos[2]["status"] == 0 and infos[2]["iters"] == 0
+    assert infos[4]["status"] == 2
+    for j in (0, 3, 5):
+        xo, io = oracle.pcg(a, B[:, j])
+        assert infos[j]["status"] == 0 and abs(infos[j]["iters"] - io["iters"]) <= 2
+        assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_multi_rhs_limit_and_replacement(cuda):
+    from paper_1107_0538_amd import Solver
+
+    a = mat(16)
+    B = W.multi_rhs(a.n, 4, seed=5)
+    s = Solver(a)
+    X, infos = s.solve_multi(_t(B, cuda), maxit=3)
+    for j in range(4):
+        xo, io = oracle.pcg(a, B[:, j], maxit=3)
+        assert infos[j]["status"] == io["status"] == 1 and infos[j]["iters"] == 3
+        assert np.linalg.norm(X.cpu().numpy()[:, j] - xo) <= 1e-9 * np.linalg.norm(xo)
+    X, infos = s.solve_multi(_t(B, cuda), tol=1e-16, maxit=400)
+    for j in range(4):
+        xo, io = oracle.pcg(a, B[:, j], tol=1e-16, maxit=400)
+        assert infos[j]["status"] == io["status"] == 1
+        assert infos[j]["replacements"] >= 1 and io["replacements"] >= 1
+        assert infos[j]["relres_true"] <= 1e-10
