@@ -80,7 +80,8 @@ typedef struct {
     int32_t block_size;    /* 0 = default; else 256, 512 or 1024 threads per workgroup  */
     int32_t chunk;         /* 0 = default; CG iterations per launched hipGraph chunk    */
     int32_t form;          /* CG_FORM_STANDARD (default) or CG_FORM_SINGLE_REDUCTION    */
-    int32_t reserved[7];
+    int32_t lanes_per_row; /* batched solver: lanes per CSR row, 8, 16 or 32 (0 = 16)  */
+    int32_t reserved[6];
 } cg_opts;
 
 /* Result of a solve. */
@@ -107,6 +108,7 @@ typedef struct {
 } cg_config;
 
 typedef struct cg_ctx cg_ctx;
+typedef struct cg_batch cg_batch;
 
 /* Fill *opts with defaults: Jacobi, no FP32 copy, no autotune, no history. */
 void cg_opts_default(cg_opts *opts);
@@ -179,6 +181,97 @@ int spmm(cg_ctx *ctx, const double *X, double *Y, int32_t s);
  */
 int cg_solve_multi(cg_ctx *ctx, const double *B, double *X, int32_t s, double tol, int32_t maxit,
                    cg_info *info);
+
+/*
+ * Batched solves: nsys independent SPD systems solved together in one
+ * persistent kernel launch (captured in a hipGraph).  systems[s] must be in
+ * host memory (mem = CG_MEM_HOST) and is validated like cg_create's input;
+ * the systems are copied into one block-diagonal device CSR.  Each system is
+ * solved by a team of workgroups sized in proportion to its expected work,
+ * with cg_solve's algorithm and stopping rules.  opts->precond applies to
+ * every system; opts->lanes_per_row picks the product's lanes per row.
+ * Returns 0, CG_EINVAL, CG_EDIAG (some system lacks a positive diagonal),
+ * CG_ENOMEM or CG_EHIP.
+ */
+int cg_batch_create(int32_t nsys, const cg_csr *systems, const cg_opts *opts, void *hip_stream,
+                    cg_batch **out);
+
+/*
+ * Solve every system: b_cat and x_cat are device vectors holding the systems'
+ * right-hand sides / initial guesses concatenated in system order (system s
+ * starts at cg_batch_offset(batch, s)); x_cat receives the solutions.  maxit
+ * <= 0 means each system's own n.  info, if not NULL, receives nsys records.
+ * Returns CG_CONVERGED if all converged, else the largest system status, or
+ * CG_ETIMEOUT if a team wait exceeded its limit.  Synchronises the stream.
+ */
+int cg_batch_solve(cg_batch *batch, const double *b_cat, double *x_cat, double tol, int32_t maxit,
+                   cg_info *info);
+
+/* Row offset of system s in the concatenated vectors (s = nsys gives the total). */
+int64_t cg_batch_offset(const cg_batch *batch, int32_t s);
+
+/* Workgroups per system (team_sizes[nsys]); returns the total grid. */
+int cg_batch_teams(const cg_batch *batch, int32_t *team_sizes);
+
+/* Detail of the last error on this batch ("" if none). */
+const char *cg_batch_last_error(const cg_batch *batch);
+
+/* Free the batch.  NULL is ignored. */
+void cg_batch_destroy(cg_batch *batch);
+
+/*
+ * Dense FP64 products of the learned warm start (proper orthogonal
+ * decomposition by the method of snapshots, and decoding coefficients into a
+ * start vector).  All pointers are device memory, row-major with the given
+ * leading dimensions; the call is asynchronous on hip_stream (NULL = default
+ * stream).  Returns 0, CG_EINVAL (NULL pointer, n < 0, a width <= 0, or a
+ * leading dimension smaller than its width), CG_ENOMEM or CG_EHIP.
+ *
+ * dense_gram:  C (ka x kb, row-major, leading dimension kb) = A' B with
+ *              A n x ka (lda), B n x kb (ldb).  The n rows are summed in
+ *              fixed chunks and the chunk partials in chunk order, so the
+ *              result is deterministic.  Uses stream-ordered scratch.
+ * dense_gemm:  C (n x m, ldc) = A W with A n x k (lda), W k x m (row-major).
+ */
+int dense_gram(const double *A, int64_t n, int32_t ka, int64_t lda, const double *B, int32_t kb, int64_t ldb,
+               double *C, void *hip_stream);
+int dense_gemm(const double *A, int64_t n, int32_t k, int64_t lda, const double *W, int32_t m, double *C,
+               int64_t ldc, void *hip_stream);
+
+/*
+ * Multilayer perceptron of the learned warm start (maps source parameters to
+ * POD coefficients): nlayers affine layers with dims[0..nlayers] widths,
+ * SiLU after every hidden layer, linear output, loss = mean squared error
+ * sum((Y - T)^2) / (batch * dims[nlayers]), Adam with bias correction.
+ * Parameters are one flat FP32 vector, per layer W (dims[l+1] x dims[l],
+ * row-major) then b (dims[l+1]).
+ * precision 0: FP32 throughout.  precision 1: BF16 weights and hidden
+ * activations (round to nearest even from FP32 master weights), products
+ * accumulated in FP32, gradients and Adam state FP32.
+ * Batches X (batch x dims[0]), T and Y (batch x dims[nlayers]) are FP32,
+ * row-major, device memory; 1 <= batch <= max_batch.  Calls are ordered on
+ * hip_stream; mlp_forward and mlp_train_step with loss == NULL do not
+ * synchronise.  Returns 0, CG_EINVAL, CG_ENOMEM or CG_EHIP.
+ */
+typedef struct mlp_net mlp_net;
+int mlp_create(int32_t nlayers, const int32_t *dims, int32_t precision, int32_t max_batch, void *hip_stream,
+               mlp_net **out);
+/* Number of parameters (or CG_EINVAL for NULL). */
+int64_t mlp_param_count(const mlp_net *net);
+/* Load parameters from host memory (FP32, flat order above); resets Adam. */
+int mlp_set_params(mlp_net *net, const float *host_params);
+/* Copy the FP32 master parameters to host memory. */
+int mlp_get_params(mlp_net *net, float *host_params);
+/* Y = network(X). */
+int mlp_forward(mlp_net *net, const float *X, int32_t batch, float *Y);
+/* Gradient of the loss at (X, T) into host memory (flat order, may be NULL);
+ * *loss (may be NULL) receives the loss in FP64.  Synchronises the stream. */
+int mlp_gradients(mlp_net *net, const float *X, const float *T, int32_t batch, float *host_grads, double *loss);
+/* One Adam step on the gradient at (X, T); *loss as in mlp_gradients. */
+int mlp_train_step(mlp_net *net, const float *X, const float *T, int32_t batch, float lr, float beta1, float beta2,
+                   float eps, double *loss);
+/* Free the network.  NULL is ignored. */
+void mlp_destroy(mlp_net *net);
 
 /* Copy up to `cap` entries of the last solve's residual history
  * (||r_k|| / ||b||, k = 0..iters) into host memory; returns the count

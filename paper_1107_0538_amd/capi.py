@@ -32,7 +32,7 @@ class cg_opts(ctypes.Structure):
     _fields_ = [("precond", ctypes.c_int32), ("fp32_copy", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("nnz_per_lane", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("history", ctypes.c_int32), ("block_size", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("form", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class cg_info(ctypes.Structure):
@@ -64,6 +64,25 @@ SIGNATURES = {
     "spmm": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "cg_solve_multi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                       ctypes.POINTER(cg_info)]),
+    "cg_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(cg_opts), _P, ctypes.POINTER(_P)]),
+    "cg_batch_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(cg_info)]),
+    "cg_batch_offset": (ctypes.c_int64, [_P, ctypes.c_int32]),
+    "cg_batch_teams": (ctypes.c_int, [_P, _P]),
+    "cg_batch_last_error": (ctypes.c_char_p, [_P]),
+    "cg_batch_destroy": (None, [_P]),
+    "dense_gram": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int32,
+                                  ctypes.c_int64, _P, _P]),
+    "dense_gemm": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int32, _P,
+                                  ctypes.c_int64, _P]),
+    "mlp_create": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "mlp_param_count": (ctypes.c_int64, [_P]),
+    "mlp_set_params": (ctypes.c_int, [_P, _P]),
+    "mlp_get_params": (ctypes.c_int, [_P, _P]),
+    "mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    "mlp_gradients": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
+    "mlp_train_step": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.POINTER(ctypes.c_double)]),
+    "mlp_destroy": (None, [_P]),
     "cg_get_history": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "cg_get_config": (ctypes.c_int, [_P, ctypes.POINTER(cg_config)]),
     "cg_destroy": (None, [_P]),

@@ -1,0 +1,448 @@
+// Batched Jacobi-PCG: many independent SPD systems in one persistent launch.
+//
+// The systems are concatenated into one block-diagonal CSR (global row and
+// column indices, int32).  System s is owned by a team of workgroups sized in
+// proportion to its expected work (nonzeros times an iteration count that
+// grows with the grid size); every team runs the full solve of the FP64
+// oracle's loop (pcg_team, residual replacement included) on its own rows,
+// meeting at its own grid barrier between steps -- a team of one workgroup
+// needs only __syncthreads.  The launch is captured in a hipGraph together
+// with the kernel that clears the barriers, so one graph launch solves the
+// whole batch.  All teams are co-resident (the grid stays within half the
+// occupancy limit) and every barrier wait is bounded.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "context.hpp"
+
+namespace jpcg {
+
+struct BatchArgs {
+    const int* __restrict__ rowptr;  // global, N_total + 1
+    const int* __restrict__ col;     // global column indices
+    const double* __restrict__ val;
+    const double* __restrict__ dinv;
+    const double* b;
+    double* x;
+    double* r;
+    double* z;
+    double* p0;
+    double* p1;
+    double* q;
+    const int2* block_team;  // per workgroup: (system, member)
+    const int* team_size;    // per system
+    const int* part_off;     // per system: offset of its NSLOT * team_size partials
+    const int* blk_row;      // per workgroup: first global row; last entry = N_total
+    const int* sys_rows;     // per system: number of rows
+    GridBarrier* bar;        // per system
+    double* part;
+    DevInfo* info;           // per system
+    double tol;
+    int maxit;               // <= 0: each system's own n
+    long long limit;
+};
+
+template <int LPR, int BS>
+__global__ __launch_bounds__(BS) void k_batch(BatchArgs a)
+{
+    __shared__ double lds[(BS / kWave) * 4];
+    __shared__ int s_flag;
+    const int2 bt = a.block_team[blockIdx.x];
+    const int sys = bt.x;
+    Team t;
+    t.bar = a.bar + sys;
+    t.part = a.part + a.part_off[sys];
+    t.G = a.team_size[sys];
+    t.L = bt.y;
+    t.gen = threadIdx.x == 0 ? barrier_gen(t.bar) : 0u;
+    t.limit = a.limit;
+    t.s_flag = &s_flag;
+    const int rs = a.blk_row[blockIdx.x], re = a.blk_row[blockIdx.x + 1];
+    SysView<double> v{0, a.rowptr, a.col, a.val, a.dinv, a.b, a.x, a.r, a.z, a.p0, a.p1, a.q};
+    const int maxit = a.maxit > 0 ? a.maxit : a.sys_rows[sys];
+    const int st = pcg_team<LPR, BS, double>(v, t, rs, re, a.tol, maxit, lds, a.info + sys, nullptr);
+    if (st == CG_ETIMEOUT && threadIdx.x == 0 && t.L == 0) a.info[sys].status = CG_ETIMEOUT;
+}
+
+// Zero the barrier words (a kernel, not a memset: the graph replays it).
+__global__ void k_batch_clear(unsigned* words, int count)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) words[i] = 0u;
+}
+
+__global__ void k_batch_jacobi(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
+                               const double* __restrict__ val, int jacobi, double* __restrict__ dinv,
+                               int* __restrict__ bad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double inv = 1.0;
+    if (jacobi) {
+        double d = 0.0;
+        int found = 0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] == i) {
+                d += val[k];
+                found = 1;
+            }
+        if (!found || !(d > 0.0)) atomicOr(bad, 1);
+        inv = 1.0 / d;
+    }
+    dinv[i] = inv;
+}
+
+constexpr int kBatchBS = 256;
+
+}  // namespace jpcg
+
+struct cg_batch {
+    hipStream_t stream = nullptr;
+    int nsys = 0;
+    int64_t n_total = 0;
+    int64_t nnz_total = 0;
+    int lpr = 16;
+    int grid = 0;
+    std::vector<int64_t> row_off;  // nsys + 1
+    std::vector<int> team;         // team sizes
+    int* rowptr = nullptr;
+    int* col = nullptr;
+    double* val = nullptr;
+    double* dinv = nullptr;
+    double* vec = nullptr;  // b, x, r, z, p0, p1, q: 7 N_total
+    int2* block_team = nullptr;
+    int* ints = nullptr;    // team_size, part_off, blk_row, sys_rows
+    jpcg::GridBarrier* bar = nullptr;
+    double* part = nullptr;
+    jpcg::DevInfo* info = nullptr;
+    jpcg::DevInfo* hinfo = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double graph_tol = -1.0;
+    int graph_maxit = -2;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    jpcg::BatchArgs args{};
+    long long limit = 0;
+    std::string err;
+};
+
+namespace jpcg {
+
+static void free_batch(cg_batch* b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    void* ptrs[] = {b->rowptr, b->col, b->val, b->dinv, b->vec, b->block_team, b->ints, b->bar, b->part, b->info};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (b->hinfo) (void)hipHostFree(b->hinfo);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    delete b;
+}
+
+static const void* batch_kernel(int lpr)
+{
+    switch (lpr) {
+        case 8: return (const void*)k_batch<8, kBatchBS>;
+        case 16: return (const void*)k_batch<16, kBatchBS>;
+        case 32: return (const void*)k_batch<32, kBatchBS>;
+        default: return nullptr;
+    }
+}
+
+static void capture_batch(cg_batch* b, double tol, int maxit)
+{
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    b->args.tol = tol;
+    b->args.maxit = maxit;
+    hipStream_t cap;
+    JPCG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph;
+    JPCG_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    unsigned* words = (unsigned*)b->bar;
+    int count = (int)(sizeof(GridBarrier) / sizeof(unsigned)) * b->nsys;
+    void* cargs[] = {&words, &count};
+    JPCG_HIP(hipLaunchKernel((const void*)k_batch_clear, dim3(std::min(1024, (count + 255) / 256)), dim3(256), cargs,
+                             0, cap));
+    void* kargs[] = {&b->args};
+    JPCG_HIP(hipLaunchKernel(batch_kernel(b->lpr), dim3(b->grid), dim3(kBatchBS), kargs, 0, cap));
+    JPCG_HIP(hipStreamEndCapture(cap, &graph));
+    hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    JPCG_HIP(hipStreamDestroy(cap));
+    JPCG_HIP(e);
+    b->graph_tol = tol;
+    b->graph_maxit = maxit;
+}
+
+}  // namespace jpcg
+
+using namespace jpcg;
+
+extern "C" {
+
+int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, void* hip_stream, cg_batch** out)
+{
+    if (!out) return CG_EINVAL;
+    *out = nullptr;
+    if (nsys <= 0 || !systems) return CG_EINVAL;
+    cg_opts o;
+    if (opts) o = *opts; else cg_opts_default(&o);
+    if (o.precond == CG_PRECOND_DEFAULT) o.precond = CG_PRECOND_JACOBI;
+    if (o.precond != CG_PRECOND_JACOBI && o.precond != CG_PRECOND_NONE) return CG_EINVAL;
+    cg_batch* b = nullptr;
+    try {
+        b = new cg_batch();
+        b->stream = (hipStream_t)hip_stream;
+        b->nsys = nsys;
+        b->lpr = o.lanes_per_row ? o.lanes_per_row : 16;
+        if (!batch_kernel(b->lpr)) {
+            free_batch(b);
+            return CG_EINVAL;
+        }
+        // Validate and concatenate on the host.
+        b->row_off.assign(nsys + 1, 0);
+        std::vector<int64_t> nnz_off(nsys + 1, 0);
+        for (int s = 0; s < nsys; ++s) {
+            const cg_csr& A = systems[s];
+            if (A.n <= 0 || A.nnz < 0 || !A.rowptr || (A.nnz > 0 && (!A.col || !A.val)) || A.mem != CG_MEM_HOST) {
+                free_batch(b);
+                return CG_EINVAL;
+            }
+            b->row_off[s + 1] = b->row_off[s] + A.n;
+            nnz_off[s + 1] = nnz_off[s] + A.nnz;
+        }
+        b->n_total = b->row_off[nsys];
+        b->nnz_total = nnz_off[nsys];
+        if (b->n_total >= 0x7fffffffLL || b->nnz_total >= 0x7fffffffLL) {
+            free_batch(b);
+            return CG_EINVAL;
+        }
+        const int N = (int)b->n_total;
+        std::vector<int> rowptr(N + 1);
+        std::vector<int> col(b->nnz_total);
+        for (int s = 0; s < nsys; ++s) {
+            const cg_csr& A = systems[s];
+            const int ro = (int)b->row_off[s], ko = (int)nnz_off[s];
+            if (A.rowptr[0] != 0 || A.rowptr[A.n] != A.nnz) {
+                free_batch(b);
+                return CG_EINVAL;
+            }
+            for (int i = 0; i < A.n; ++i) {
+                if (A.rowptr[i + 1] < A.rowptr[i]) {
+                    free_batch(b);
+                    return CG_EINVAL;
+                }
+                rowptr[ro + i] = ko + A.rowptr[i];
+            }
+            for (int64_t k = 0; k < A.nnz; ++k) {
+                if (A.col[k] < 0 || A.col[k] >= A.n) {
+                    free_batch(b);
+                    return CG_EINVAL;
+                }
+                col[ko + k] = ro + A.col[k];
+            }
+        }
+        rowptr[N] = (int)b->nnz_total;
+
+        // Teams: workgroups per system in proportion to nnz times rows^(1/3)
+        // (CG iterations grow with the grid edge), within half the occupancy.
+        int dev = 0, cus = 0, per_cu = 0, wall_khz = 0;
+        JPCG_HIP(hipGetDevice(&dev));
+        JPCG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        JPCG_HIP(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev));
+        JPCG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(b->lpr), kBatchBS, 0));
+        b->limit = (long long)std::max(wall_khz, 1000) * 1000LL * 8;  // 8 s of device wall clock
+        const int capacity = std::max(nsys, std::max(1, per_cu * cus / 2));
+        std::vector<double> work(nsys);
+        double total = 0.0;
+        for (int s = 0; s < nsys; ++s) {
+            const double n_s = (double)systems[s].n, z_s = (double)systems[s].nnz;
+            work[s] = (z_s + n_s) * std::cbrt(n_s);
+            total += work[s];
+        }
+        b->team.assign(nsys, 1);
+        int used = nsys;
+        for (int s = 0; s < nsys; ++s) {
+            const int want = std::max(1, (int)std::floor(work[s] / total * capacity));
+            const int rows_cap = std::max(1, systems[s].n / 64);  // at least 64 rows per workgroup
+            const int extra = std::min(want, rows_cap) - 1;
+            if (used + extra <= capacity) {
+                b->team[s] += extra;
+                used += extra;
+            }
+        }
+        b->grid = used;
+        // Per-workgroup tables.
+        std::vector<int2> block_team(used);
+        std::vector<int> blk_row(used + 1), team_size(nsys), part_off(nsys), sys_rows(nsys);
+        int blk = 0, poff = 0;
+        for (int s = 0; s < nsys; ++s) {
+            const cg_csr& A = systems[s];
+            const int T = b->team[s];
+            team_size[s] = T;
+            part_off[s] = poff;
+            poff += NSLOT * T;
+            sys_rows[s] = A.n;
+            std::vector<int> local_rp(A.rowptr, A.rowptr + A.n + 1), rows;
+            partition_rows(local_rp, T, rows);
+            for (int L = 0; L < T; ++L) {
+                block_team[blk] = int2{s, L};
+                blk_row[blk] = (int)b->row_off[s] + rows[L];
+                ++blk;
+            }
+        }
+        blk_row[used] = N;
+
+        // Device copies.
+        JPCG_HIP(hipMalloc(&b->rowptr, sizeof(int) * (N + 1)));
+        JPCG_HIP(hipMalloc(&b->col, sizeof(int) * std::max<int64_t>(b->nnz_total, 1)));
+        JPCG_HIP(hipMalloc(&b->val, sizeof(double) * std::max<int64_t>(b->nnz_total, 1)));
+        JPCG_HIP(hipMalloc(&b->dinv, sizeof(double) * N));
+        JPCG_HIP(hipMalloc(&b->vec, sizeof(double) * 7 * (size_t)N));
+        JPCG_HIP(hipMalloc(&b->block_team, sizeof(int2) * used));
+        JPCG_HIP(hipMalloc(&b->ints, sizeof(int) * (3 * (size_t)nsys + used + 1)));
+        JPCG_HIP(hipMalloc(&b->bar, sizeof(GridBarrier) * nsys));
+        JPCG_HIP(hipMalloc(&b->part, sizeof(double) * std::max(poff, 1)));
+        JPCG_HIP(hipMalloc(&b->info, sizeof(DevInfo) * nsys));
+        JPCG_HIP(hipHostMalloc(&b->hinfo, sizeof(DevInfo) * nsys, hipHostMallocDefault));
+        JPCG_HIP(hipEventCreate(&b->ev0));
+        JPCG_HIP(hipEventCreate(&b->ev1));
+        hipStream_t st = b->stream;
+        JPCG_HIP(hipMemcpyAsync(b->rowptr, rowptr.data(), sizeof(int) * (N + 1), hipMemcpyHostToDevice, st));
+        JPCG_HIP(hipMemcpyAsync(b->col, col.data(), sizeof(int) * b->nnz_total, hipMemcpyHostToDevice, st));
+        for (int s = 0; s < nsys; ++s)
+            JPCG_HIP(hipMemcpyAsync(b->val + nnz_off[s], systems[s].val, sizeof(double) * systems[s].nnz,
+                                    hipMemcpyHostToDevice, st));
+        JPCG_HIP(hipMemsetAsync(b->vec, 0, sizeof(double) * 7 * (size_t)N, st));
+        JPCG_HIP(hipMemcpyAsync(b->block_team, block_team.data(), sizeof(int2) * used, hipMemcpyHostToDevice, st));
+        int* d_team = b->ints;
+        int* d_poff = d_team + nsys;
+        int* d_rows = d_poff + nsys;
+        int* d_blk = d_rows + nsys;
+        JPCG_HIP(hipMemcpyAsync(d_team, team_size.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st));
+        JPCG_HIP(hipMemcpyAsync(d_poff, part_off.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st));
+        JPCG_HIP(hipMemcpyAsync(d_rows, sys_rows.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st));
+        JPCG_HIP(hipMemcpyAsync(d_blk, blk_row.data(), sizeof(int) * (used + 1), hipMemcpyHostToDevice, st));
+        int* bad = nullptr;
+        JPCG_HIP(hipMalloc(&bad, sizeof(int)));
+        JPCG_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+        k_batch_jacobi<<<(N + 255) / 256, 256, 0, st>>>(N, b->rowptr, b->col, b->val, o.precond == CG_PRECOND_JACOBI,
+                                                       b->dinv, bad);
+        JPCG_HIP(hipGetLastError());
+        int hbad = 0;
+        JPCG_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        JPCG_HIP(hipStreamSynchronize(st));
+        JPCG_HIP(hipFree(bad));
+        if (hbad) {
+            free_batch(b);
+            return CG_EDIAG;
+        }
+        double* v = b->vec;
+        BatchArgs& a = b->args;
+        a.rowptr = b->rowptr;
+        a.col = b->col;
+        a.val = b->val;
+        a.dinv = b->dinv;
+        a.b = v;
+        a.x = v + (size_t)N;
+        a.r = v + 2 * (size_t)N;
+        a.z = v + 3 * (size_t)N;
+        a.p0 = v + 4 * (size_t)N;
+        a.p1 = v + 5 * (size_t)N;
+        a.q = v + 6 * (size_t)N;
+        a.block_team = b->block_team;
+        a.team_size = d_team;
+        a.part_off = d_poff;
+        a.blk_row = d_blk;
+        a.sys_rows = d_rows;
+        a.bar = b->bar;
+        a.part = b->part;
+        a.info = b->info;
+        a.limit = b->limit;
+        *out = b;
+        return 0;
+    } catch (const HipError& e) {
+        free_batch(b);
+        return e.code == hipErrorOutOfMemory ? CG_ENOMEM : CG_EHIP;
+    } catch (const std::bad_alloc&) {
+        free_batch(b);
+        return CG_ENOMEM;
+    }
+}
+
+int cg_batch_solve(cg_batch* b, const double* b_cat, double* x_cat, double tol, int32_t maxit, cg_info* info)
+{
+    if (!b) return CG_EINVAL;
+    if (!b_cat || !x_cat || b_cat == x_cat || !(tol >= 0.0) || !std::isfinite(tol)) return CG_EINVAL;
+    try {
+        if (!b->exec || b->graph_tol != tol || b->graph_maxit != maxit) capture_batch(b, tol, maxit);
+        hipStream_t st = b->stream;
+        const size_t vb = sizeof(double) * (size_t)b->n_total;
+        JPCG_HIP(hipEventRecord(b->ev0, st));
+        JPCG_HIP(hipMemcpyAsync((void*)b->args.b, b_cat, vb, hipMemcpyDeviceToDevice, st));
+        JPCG_HIP(hipMemcpyAsync(b->args.x, x_cat, vb, hipMemcpyDeviceToDevice, st));
+        JPCG_HIP(hipGraphLaunch(b->exec, st));
+        JPCG_HIP(hipMemcpyAsync(x_cat, b->args.x, vb, hipMemcpyDeviceToDevice, st));
+        JPCG_HIP(hipEventRecord(b->ev1, st));
+        JPCG_HIP(hipMemcpyAsync(b->hinfo, b->info, sizeof(DevInfo) * b->nsys, hipMemcpyDeviceToHost, st));
+        JPCG_HIP(hipStreamSynchronize(st));
+        float ms = 0.f;
+        JPCG_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+        int worst = CG_CONVERGED;
+        bool timeout = false;
+        for (int s = 0; s < b->nsys; ++s) {
+            const DevInfo& d = b->hinfo[s];
+            if (d.status == CG_ETIMEOUT) timeout = true;
+            else worst = std::max(worst, d.status);
+            if (info) {
+                const double nb = std::sqrt(d.bb);
+                info[s].iters = d.iters;
+                info[s].status = d.status;
+                info[s].replacements = d.replacements;
+                info[s].outer = 0;
+                info[s].relres_recur = nb > 0 ? std::sqrt(d.rr_recur) / nb : 0.0;
+                info[s].relres_true = nb > 0 ? std::sqrt(d.rr_true) / nb : 0.0;
+                info[s].seconds = ms * 1e-3;
+            }
+        }
+        if (timeout) {
+            b->err = "a team barrier timed out";
+            return CG_ETIMEOUT;
+        }
+        return worst;
+    } catch (const HipError& e) {
+        b->err = std::string("cg_batch_solve: ") + e.what + ": " + hipGetErrorString(e.code);
+        return CG_EHIP;
+    }
+}
+
+int64_t cg_batch_offset(const cg_batch* b, int32_t s)
+{
+    if (!b || s < 0 || s > b->nsys) return CG_EINVAL;
+    return b->row_off[s];
+}
+
+int cg_batch_teams(const cg_batch* b, int32_t* team_sizes)
+{
+    if (!b || !team_sizes) return CG_EINVAL;
+    for (int s = 0; s < b->nsys; ++s) team_sizes[s] = b->team[s];
+    return b->grid;
+}
+
+const char* cg_batch_last_error(const cg_batch* b) { return b ? b->err.c_str() : ""; }
+
+void cg_batch_destroy(cg_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    free_batch(b);
+}
+
+}  // extern "C"

@@ -193,3 +193,62 @@ class Solver:
         c = capi.cg_config()
         capi.check(self._lib.cg_get_config(self.ctx, ctypes.byref(c)), self.ctx)
         return c.as_dict()
+
+
+class Batch:
+    """A cg_batch: many independent SPD CSR systems solved in one launch."""
+
+    def __init__(self, systems, precond="jacobi", lanes_per_row=0, stream=None):
+        torch = _torch()
+        self._lib = capi.load()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.nsys = len(systems)
+        arr = (capi.cg_csr * self.nsys)()
+        self._keep = []
+        for i, a in enumerate(systems):
+            csr, keep = make_csr(a)
+            if csr.mem != capi.CG_MEM_HOST:
+                raise ValueError("batched systems must be host (numpy) CSR matrices")
+            arr[i] = csr
+            self._keep.append(keep)
+        opts = make_opts(precond)
+        opts.lanes_per_row = int(lanes_per_row)
+        h = ctypes.c_void_p()
+        rc = self._lib.cg_batch_create(self.nsys, arr, ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(h))
+        self._keep = None
+        capi.check(rc)
+        self.h = h
+        self.offsets = [int(self._lib.cg_batch_offset(h, s)) for s in range(self.nsys + 1)]
+        self.n_total = self.offsets[-1]
+
+    def teams(self):
+        t = (ctypes.c_int32 * self.nsys)()
+        grid = self._lib.cg_batch_teams(self.h, t)
+        return list(t), grid
+
+    def cg_solve(self, b_cat, x_cat, tol=1e-10, maxit=0):
+        _as_device_vec(b_cat, self.n_total, "b_cat")
+        _as_device_vec(x_cat, self.n_total, "x_cat")
+        infos = (capi.cg_info * self.nsys)()
+        rc = self._lib.cg_batch_solve(self.h, b_cat.data_ptr(), x_cat.data_ptr(), float(tol), int(maxit), infos)
+        if rc < 0:
+            raise capi.CGError(rc, self._lib.cg_batch_last_error(self.h).decode())
+        return [infos[s].as_dict() for s in range(self.nsys)]
+
+    def solve(self, b_cat, x0=None, tol=1e-10, maxit=0):
+        torch = _torch()
+        x = torch.zeros_like(b_cat) if x0 is None else x0.clone()
+        infos = self.cg_solve(b_cat, x, tol, maxit)
+        return x, infos
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.cg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,104 @@
+"""Batched form: independent systems of uneven size in one persistent launch.
+
+Each system is judged against its own FP64 oracle solve with the single-system
+criteria (+-2 iterations, solution within 1e-8, true relres <= 1e-10).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from conftest import TOL_RECOMPUTED
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a), device=dev)
+
+
+def small_batch(count=12, seed=7):
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(count):
+        n = int(rng.integers(2, 17))
+        a, b = W.problem(n, seed * 100 + s)
+        out.append((a, b))
+    return out
+
+
+def check_system(a, b, x, info):
+    xo, io = oracle.pcg(a, b)
+    assert info["status"] == 0 and io["status"] == 0
+    assert abs(info["iters"] - io["iters"]) <= 2, (info, io)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+    assert oracle.relres(a, b, x) <= TOL_RECOMPUTED
+
+
+@pytest.mark.parametrize("lpr", [8, 16, 32])
+def test_small_batch_parity(cuda, lpr):
+    from paper_1107_0538_amd import Batch
+
+    sys = small_batch()
+    bt = Batch([a for a, _ in sys], lanes_per_row=lpr)
+    b_cat = np.concatenate([b for _, b in sys])
+    x, infos = bt.solve(_t(b_cat, cuda))
+    x = x.cpu().numpy()
+    for s, (a, b) in enumerate(sys):
+        check_system(a, b, x[bt.offsets[s]:bt.offsets[s + 1]], infos[s])
+    # Deterministic and repeatable through the graph.
+    x2, infos2 = bt.solve(_t(b_cat, cuda))
+    assert np.array_equal(x, x2.cpu().numpy())
+    assert [i["iters"] for i in infos] == [i["iters"] for i in infos2]
+
+
+def test_batch_isolates_bad_systems(cuda):
+    from paper_1107_0538_amd import Batch
+
+    sys = small_batch(6, seed=3)
+    bs = [b.copy() for _, b in sys]
+    bs[1][:] = 0.0
+    bs[4][2] = np.nan
+    bt = Batch([a for a, _ in sys])
+    x, infos = bt.solve(_t(np.concatenate(bs), cuda))
+    x = x.cpu().numpy()
+    assert infos[1]["status"] == 0 and infos[1]["iters"] == 0
+    assert not x[bt.offsets[1]:bt.offsets[2]].any()
+    assert infos[4]["status"] == 2
+    for s in (0, 2, 3, 5):
+        check_system(sys[s][0], bs[s], x[bt.offsets[s]:bt.offsets[s + 1]], infos[s])
+
+
+def test_batch_rejects_bad_input(cuda):
+    from paper_1107_0538_amd import Batch, capi
+
+    a, _ = W.problem(4, 0)
+    bad = W.CSR(2, np.array([0, 1, 2], np.int32), np.array([0, 1], np.int32), np.array([0.0, 1.0]))
+    with pytest.raises(capi.CGError):
+        Batch([a, bad])
+    broken = W.CSR(2, np.array([0, 1, 2], np.int32), np.array([0, 5], np.int32), np.array([1.0, 1.0]))
+    with pytest.raises(ValueError):
+        Batch([a, broken])
+
+
+def test_batch_256_uneven_systems(cuda):
+    # The batched workload: 256 systems, edge n ~ U{12..48}, seeds 1000 + s.
+    from paper_1107_0538_amd import Batch
+
+    sys = W.batch_systems(256)
+    bt = Batch([a for _, a, _ in sys])
+    teams, grid = bt.teams()
+    assert len(teams) == 256 and min(teams) >= 1 and grid == sum(teams)
+    b_cat = np.concatenate([b for _, _, b in sys])
+    x, infos = bt.solve(_t(b_cat, cuda))
+    x = x.cpu().numpy()
+    for s, (n, a, b) in enumerate(sys):
+        xs = x[bt.offsets[s]:bt.offsets[s + 1]]
+        assert infos[s]["status"] == 0
+        assert oracle.relres(a, b, xs) <= TOL_RECOMPUTED
+    sizes = np.array([n for n, _, _ in sys])
+    for s in [int(np.argmin(sizes)), int(np.argmax(sizes)), 5, 100, 200]:
+        n, a, b = sys[s]
+        check_system(a, b, x[bt.offsets[s]:bt.offsets[s + 1]], infos[s])
