@@ -42,7 +42,8 @@ constexpr int kCols = 64;
 struct MrState {
     int stop;          // no column active
     int any_pending;
-    int pad[2];
+    int kk;            // iterations completed (the next one is kk + 1, parity (kk + 1) & 1)
+    int pad;
     int status[kCols];
     int iters[kCols];
     int repl[kCols];
@@ -284,6 +285,7 @@ __global__ __launch_bounds__(256) void k_mr_scalars(MrArgs<T> a, int phase)
     int status = j < a.s ? st->status[j] : COL_UNUSED;
     if (phase == MR_SETUP) {
         // g = (r'r, r'z, b'b) of r0
+        if (j == 0) st->kk = 0;
         st->repl[j] = 0;
         st->iters[j] = 0;
         st->first[j] = 1;
@@ -316,6 +318,7 @@ __global__ __launch_bounds__(256) void k_mr_scalars(MrArgs<T> a, int phase)
         }
     } else if (phase == MR_ITER) {
         // g = (r'z, r'r) after the update: the oracle's order of tests.
+        if (j == 0) st->kk += 1;
         if (status == COL_ACTIVE) {
             st->iters[j] += 1;
             st->first[j] = 0;
@@ -568,6 +571,10 @@ int cg_solve_multi(cg_ctx* c, const double* B, double* X, int32_t s, double tol,
         long long launched = 0;
         while (true) {
             MrState h = mr_read(c, m);
+            // Iterations after the stop flag was raised returned early, so the
+            // next iteration's parity comes from the device's count, not from
+            // the number of iterations launched.
+            next = h.kk + 1;
             if (h.stop) {
                 if (!h.any_pending) break;
                 mode = 1;

@@ -102,3 +102,20 @@ def test_batch_256_uneven_systems(cuda):
     for s in [int(np.argmin(sizes)), int(np.argmax(sizes)), 5, 100, 200]:
         n, a, b = sys[s]
         check_system(a, b, x[bt.offsets[s]:bt.offsets[s + 1]], infos[s])
+
+
+def test_batch_systems_with_replacement(cuda):
+    # Systems whose solves need residual replacements at tol = 1e-10.
+    from paper_1107_0538_amd import Batch
+
+    a, _ = W.problem(16, 0)
+    fam = W.amplitude_family(n=16, count=6)
+    bs = list(fam.rhs(np.arange(6)))
+    small, _ = W.problem(5, 1)
+    mats = [a] * 6 + [small]
+    bs.append(np.random.default_rng(0).uniform(-1, 1, small.n))
+    bt = Batch(mats)
+    x, infos = bt.solve(_t(np.concatenate(bs), cuda))
+    x = x.cpu().numpy()
+    for s in range(7):
+        check_system(mats[s], bs[s], x[bt.offsets[s]:bt.offsets[s + 1]], infos[s])

@@ -112,3 +112,42 @@ def test_multi_rhs_limit_and_replacement(cuda):
         assert infos[j]["status"] == io["status"] == 1
         assert infos[j]["replacements"] >= 1 and io["replacements"] >= 1
         assert infos[j]["relres_true"] <= 1e-10
+
+
+def test_multi_rhs_replacement_resume(cuda):
+    # Right-hand sides whose solves need residual replacements: a column
+    # resumes after its true-residual check while the iteration count on the
+    # host has run ahead, so the resumed direction must come from the device's
+    # own iteration parity.
+    from paper_1107_0538_amd import Solver
+
+    a = mat(16)
+    fam = W.amplitude_family(n=16, count=64)
+    B = np.ascontiguousarray(fam.rhs(np.arange(64)).T)
+    X, infos = Solver(a).solve_multi(_t(B, cuda))
+    X = X.cpu().numpy()
+    reps = 0
+    for j in range(64):
+        xo, io = oracle.pcg(a, B[:, j])
+        reps += io["replacements"]
+        assert infos[j]["status"] == io["status"] == 0, (j, infos[j], io)
+        assert abs(infos[j]["iters"] - io["iters"]) <= 2, (j, infos[j], io)
+        assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) <= 1e-8
+        assert oracle.relres(a, B[:, j], X[:, j]) <= TOL_RECOMPUTED
+    assert reps >= 32
+
+
+def test_multi_rhs_block_width_changes(cuda):
+    # One context, block widths 64, 44, 64, 5 in turn: each call matches the oracle.
+    from paper_1107_0538_amd import Solver
+
+    a = mat(16)
+    s = Solver(a)
+    for width in (64, 44, 64, 5):
+        B = W.multi_rhs(a.n, width, seed=width)
+        X, infos = s.solve_multi(_t(B, cuda))
+        X = X.cpu().numpy()
+        for j in (0, width // 2, width - 1):
+            xo, io = oracle.pcg(a, B[:, j])
+            assert infos[j]["status"] == 0 and abs(infos[j]["iters"] - io["iters"]) <= 2
+            assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) <= 1e-8

@@ -5,11 +5,13 @@ right-hand sides.
 """
 from .q1hex import (  # noqa: F401
     CSR,
+    AmplitudeFamily,
     KHAT,
     MASS_COEF,
     MHAT,
     OFFSETS,
     SourceFamily,
+    amplitude_family,
     assemble,
     batch_systems,
     element_sigma,

@@ -266,3 +266,36 @@ def source_family(n: int = 51, count: int = 2000, k: int = 8, seed: int = 3) -> 
     amps = rng.standard_normal(k)
     centres = rng.uniform(0.0, 1.0, (count, k, 3))
     return SourceFamily(n, widths, amps, centres)
+
+
+@dataclasses.dataclass
+class AmplitudeFamily:
+    """Right-hand sides b = sum_k theta_k M g_k with k fixed Gaussian sources g_k.
+
+    The solutions span exactly k directions and depend linearly on theta
+    (the network input, U[0, 1]^k).  Their large smooth part makes the
+    recurrence residual drift from the true one, so most solves need one or
+    two residual replacements at tol = 1e-10.
+    """
+
+    base: SourceFamily
+    amps: np.ndarray  # (count, k)
+
+    @property
+    def count(self) -> int:
+        return self.amps.shape[0]
+
+    def theta(self) -> np.ndarray:
+        return self.amps.copy()
+
+    def rhs(self, idx) -> np.ndarray:
+        idx = np.atleast_1d(np.asarray(idx))
+        k = self.base.widths.size
+        basis = np.stack([dataclasses.replace(self.base, amps=np.eye(k)[j]).rhs(0)[0] for j in range(k)])
+        return self.amps[idx] @ basis
+
+
+def amplitude_family(n: int = 16, count: int = 400, k: int = 4, seed: int = 11) -> AmplitudeFamily:
+    """k sources drawn as in source_family (count 1, seed), amplitudes U[0, 1] with seed + 1."""
+    base = source_family(n=n, count=1, k=k, seed=seed)
+    return AmplitudeFamily(base, np.random.default_rng(seed + 1).uniform(0.0, 1.0, (count, k)))
