@@ -237,6 +237,13 @@ int dense_gram(const double *A, int64_t n, int32_t ka, int64_t lda, const double
                double *C, void *hip_stream);
 int dense_gemm(const double *A, int64_t n, int32_t k, int64_t lda, const double *W, int32_t m, double *C,
                int64_t ldc, void *hip_stream);
+/* Decode POD coefficients into start vectors: X (n x nb, row-major) = Phi c'
+ * with Phi n x k (ldphi, FP64), coef nb x k (row-major, FP32: the network's
+ * output layout) and c_jl = scale[l] * coef_jl + shift[l] in FP64 (scale and
+ * shift are k-vectors, either may be NULL: 1 and 0); nb * k <= 4096.  Device
+ * memory, asynchronous.  Returns 0, CG_EINVAL or CG_EHIP. */
+int pod_decode(const double *Phi, int64_t n, int32_t k, int64_t ldphi, const float *coef, int32_t nb,
+               const double *scale, const double *shift, double *X, void *hip_stream);
 
 /*
  * Multilayer perceptron of the learned warm start (maps source parameters to

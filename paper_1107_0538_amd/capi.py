@@ -74,6 +74,8 @@ SIGNATURES = {
                                   ctypes.c_int64, _P, _P]),
     "dense_gemm": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int32, _P,
                                   ctypes.c_int64, _P]),
+    "pod_decode": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int32, _P, _P,
+                                  _P, _P]),
     "mlp_create": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "mlp_param_count": (ctypes.c_int64, [_P]),
     "mlp_set_params": (ctypes.c_int, [_P, _P]),
