@@ -231,6 +231,11 @@ out:
  * sigma = delta - beta * gamma / alpha.  In exact arithmetic the iterates are
  * those of oracle_pcg.  Stopping rules, statuses, history and trace follow
  * oracle_pcg (trace slots hold x, r, u, p).
+ *
+ * A residual replacement breaks the relations behind the recurred s and
+ * sigma (r no longer equals r_prev - alpha s), so the step after one forms
+ * p as usual and then takes s = A p and sigma = p's directly: the standard
+ * form's p'Ap.
  */
 int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
                   const double *b, double *x, double tol, int maxit, int precond,
@@ -293,7 +298,7 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
     memcpy(sv, w, sizeof(double) * (size_t)n);
     snapshot(trace, n, 0, x, r, u, p);
 
-    int k = 0;
+    int k = 0, replaced = 0;
     while (k < maxit) {
         if (!(sigma > 0.0) || !isfinite(sigma)) { status = ORC_BREAKDOWN; break; }
         double alpha = gamma / sigma;
@@ -314,6 +319,7 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
             }
             memcpy(r, t, sizeof(double) * (size_t)n);       /* residual replacement */
             info->replacements += 1;
+            replaced = 1;
         }
         for (int i = 0; i < n; ++i) u[i] = r[i] / diag[i];
         oracle_spmv(n, rowptr, col, val, u, w);
@@ -325,10 +331,16 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
             break;
         }
         double beta = gamma_new / gamma;
-        sigma = delta - beta * gamma_new / alpha;
         gamma = gamma_new;
         for (int i = 0; i < n; ++i) p[i] = u[i] + beta * p[i];
-        for (int i = 0; i < n; ++i) sv[i] = w[i] + beta * sv[i];
+        if (replaced) {
+            oracle_spmv(n, rowptr, col, val, p, sv);        /* s = A p */
+            sigma = oracle_dot(n, p, sv, sum_mode);         /* sigma = p'Ap */
+            replaced = 0;
+        } else {
+            sigma = delta - beta * gamma_new / alpha;
+            for (int i = 0; i < n; ++i) sv[i] = w[i] + beta * sv[i];
+        }
         snapshot(trace, n, k, x, r, u, p);
     }
     info->iters = k;

@@ -198,3 +198,21 @@ def test_single_reduction_form_tracks_standard_iterates():
     x1, i1 = oracle.pcg(a, b, form="single")
     assert abs(i0["iters"] - i1["iters"]) <= 2 and i1["relres_true"] <= 1e-10
     assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) <= 1e-8
+
+
+def test_single_reduction_form_across_replacements():
+    # Systems whose solves need residual replacements at 1e-10: after a
+    # replacement the single-reduction form takes s = A p and p'Ap directly,
+    # so it keeps tracking the standard form (within +-2 iterations, same
+    # solution to 1e-8) instead of breaking down on a recurred sigma.
+    a, _ = W.problem(14, 0)
+    fam = W.amplitude_family(n=14, count=8)
+    reps = 0
+    for b in fam.rhs(np.arange(8)):
+        x0, i0 = oracle.pcg(a, b)
+        x1, i1 = oracle.pcg(a, b, form="single")
+        reps += i1["replacements"]
+        assert i0["status"] == i1["status"] == oracle.CONVERGED
+        assert abs(i0["iters"] - i1["iters"]) <= 2
+        assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) <= 1e-8
+    assert reps >= 4

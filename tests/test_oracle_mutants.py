@@ -37,6 +37,7 @@ MUTANTS = {
     "sr_product_of_r": ("oracle_spmv(n, rowptr, col, val, u, w);\n        double gamma_new",
                         "oracle_spmv(n, rowptr, col, val, r, w);\n        double gamma_new"),
     "sr_gamma_stale": ("        gamma = gamma_new;\n", "        gamma = gamma;\n"),
+    "sr_replacement_keeps_recurrence": ("        if (replaced) {", "        if (0) {"),
 }
 
 SINGLE_FORM = {k for k in MUTANTS if k.startswith("sr_")}
@@ -73,7 +74,19 @@ def _pins_pass(form: str = "standard") -> bool:
             W.CSR(n, np.arange(0, n * n + 1, n, dtype=np.int32), np.tile(np.arange(n, dtype=np.int32), n),
                   (np.eye(n) + np.outer(u, u)).ravel()),
             rng.standard_normal(n), tol=1e-12, precond="none", form=form)
-        return info["status"] == oracle.CONVERGED and info["iters"] == 2
+        if not (info["status"] == oracle.CONVERGED and info["iters"] == 2):
+            return False
+        if form == "single":
+            # Systems that need residual replacements: the single-reduction
+            # form must converge alongside the standard one.
+            a, _ = W.problem(14, 0)
+            fam = W.amplitude_family(n=14, count=8)
+            for b in fam.rhs(np.arange(8)):
+                _, i_s = oracle.pcg(a, b)
+                _, i_r = oracle.pcg(a, b, form="single")
+                if i_r["status"] != oracle.CONVERGED or abs(i_r["iters"] - i_s["iters"]) > 2:
+                    return False
+        return True
     except Exception:
         return False
 
