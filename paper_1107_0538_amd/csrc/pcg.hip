@@ -224,7 +224,7 @@ struct cg_graphs {
     bool fp32 = false;
     int npl = 0, bs = 0, G = 0, T = 0, chunk = 0;
     int4* tiles = nullptr;
-    double* part = nullptr;  // 9G doubles, laid out per form
+    double* part = nullptr;  // 11G doubles, laid out per form
     void* st = nullptr;      // CgState or SrState
     void* hst = nullptr;     // pinned, 4 slots
     size_t st_bytes = 0;
@@ -291,7 +291,7 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
         g->st_bytes = std::max(sizeof(CgState), sizeof(SrState));
         const size_t eb = fp32 ? sizeof(float) : sizeof(double);
         JPCG_HIP(hipMalloc(&g->tiles, sizeof(int4) * std::max(T, 1)));
-        JPCG_HIP(hipMalloc(&g->part, sizeof(double) * 9 * (size_t)G));
+        JPCG_HIP(hipMalloc(&g->part, sizeof(double) * 11 * (size_t)G));
         JPCG_HIP(hipMalloc(&g->st, g->st_bytes));
         JPCG_HIP(hipHostMalloc(&g->hst, g->st_bytes * 4, hipHostMallocDefault));
         JPCG_HIP(hipMalloc(&g->cb, eb * c->n));
@@ -338,6 +338,7 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
             sa.part[1] = g->part + 3 * (size_t)G;
             sa.part_setup = g->part + 6 * (size_t)G;
             sa.part_chk = g->part + 8 * (size_t)G;
+            sa.part_rst = g->part + 9 * (size_t)G;
             sa.st = (SrState*)g->st;
             sa.hist = nullptr;
         }

@@ -13,6 +13,11 @@
 // for the u_k that the row lanes store implicitly.  The gathered vectors r, w
 // and s alternate between two buffers by iteration parity; p and x update in
 // place (no other row reads them).
+//
+// After a residual replacement the recurrences behind sigma no longer hold:
+// the restart kernel recomputes s = A p exactly and the partials of u'(A p)
+// and p'(A p), and the next kernel takes sigma = p_new' A p_new expanded as
+// delta + 2 beta u'(A p) + beta^2 p'(A p).
 #pragma once
 
 #include "tiles.hpp"
@@ -28,6 +33,7 @@ struct SrState {
     double nb, thr;
     double gam[2];    // gam[P] = gamma_{k-1}, written by K_k (P = k % 2)
     double alpha[2];  // alpha[P] = alpha_k, written by K_k
+    int rst[2];       // rst[P]: the state in parity P follows a replacement
     double rr;        // ||r||^2 at the last continue-condition test
     double rr_true;   // ||b - A x||^2 of the returned x
 };
@@ -49,6 +55,7 @@ struct SrArgs {
     double* part[2];     // [G][3]: gamma, delta, r'r from the kernel of parity P
     double* part_setup;  // [G][2]: r'r, b'b of r0
     double* part_chk;    // [G][1]: ||b - A x||^2 (check and report)
+    double* part_rst;    // [G][2]: u'(A p), p'(A p) after a replacement
     SrState* st;
     double* hist;
 };
@@ -105,6 +112,8 @@ __global__ __launch_bounds__(BS) void k_sr_first(SrArgs a, double tol, int maxit
     if (sr_leader(a)) {
         st->kk[0] = 0;
         st->kk[1] = 0;
+        st->rst[0] = 0;
+        st->rst[1] = 0;
         st->k_done = 0;
         st->maxit = maxit;
         st->replacements = 0;
@@ -164,7 +173,7 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
     int km1 = 0;
     bool go = false;
     auto prologue = [&]() -> bool {
-        const int stop = st->stop, maxit = st->maxit;
+        const int stop = st->stop, maxit = st->maxit, rst = st->rst[Q];
         km1 = st->kk[Q];
         const double thr = st->thr, nb = st->nb, gam2 = st->gam[Q], alpha1 = st->alpha[Q];
         double g[3];
@@ -185,7 +194,13 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
         else {
             if (km1 > 0) {
                 beta = gam / gam2;
-                sigma = delta - beta * gam / alpha1;
+                if (rst) {  // s was recomputed as A p after a replacement
+                    double e[2];
+                    wave_grid_sum<2>(a.part_rst, a.G, e);
+                    sigma = delta + 2.0 * beta * e[0] + beta * beta * e[1];
+                } else {
+                    sigma = delta - beta * gam / alpha1;
+                }
             }
             if (!(sigma > 0.0) || !isfinite(sigma)) code = STOP_BREAKDOWN;
         }
@@ -232,6 +247,7 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
         st->kk[P] = km1 + 1;
         st->gam[P] = gam_prev;
         st->alpha[P] = alpha;
+        st->rst[P] = 0;
     }
 }
 
@@ -277,16 +293,19 @@ __global__ __launch_bounds__(BS) void k_sr_decide(SrArgs a, int report)
 }
 
 // After a replacement: w = A M^-1 r for the replaced r in R[P], with the
-// partials of (gamma, delta, r'r) in part[P] for the next iteration.
+// partials of (gamma, delta, r'r) in part[P] for the next iteration; then
+// s = A p into S[P] with the partials of u'(A p) and p'(A p) in part_rst.
 template <int NPL, int BS>
 __global__ __launch_bounds__(BS) void k_sr_restart(SrArgs a, int P)
 {
     __shared__ SrLds<NPL, BS> sh;
     const double* __restrict__ r = a.R[P];
     const double* __restrict__ dinv = a.dinv;
+    const double* __restrict__ p = a.p;
+    double* prod = sh.prod + (threadIdx.x / kWave) * (kWave * NPL);
     double v[3] = {0.0, 0.0, 0.0};
     tile_rows<NPL, double>(
-        a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
+        a.rowptr, a.col, a.val, a.tm, sr_logical(a), prod,
         [&](int j) { return Pair2{r[j], dinv[j]}; }, [&](Pair2 rd) { return rd.b * rd.a; },
         [&](int i) { return Pair2{r[i], dinv[i]}; },
         [&](int i, double wi, Pair2 rd) {
@@ -297,7 +316,19 @@ __global__ __launch_bounds__(BS) void k_sr_restart(SrArgs a, int P)
             v[2] += rd.a * rd.a;
         },
         NoPrologue{});
+    double e[2] = {0.0, 0.0};
+    tile_rows<NPL, double>(
+        a.rowptr, a.col, a.val, a.tm, sr_logical(a), prod, [&](int j) { return p[j]; }, Ident<double>{},
+        [&](int i) { return Pair2{p[i], dinv[i] * r[i]}; },
+        [&](int i, double si, Pair2 pu) {
+            a.S[P][i] = si;
+            e[0] += pu.b * si;
+            e[1] += pu.a * si;
+        },
+        NoPrologue{});
     block_partials<BS, 3>(v, sh.red, a.part[P], sr_logical(a));
+    block_partials<BS, 2>(e, sh.red, a.part_rst, sr_logical(a));
+    if (sr_leader(a)) a.st->rst[P] = 1;
 }
 
 }  // namespace jpcg
