@@ -5,6 +5,12 @@ Workload: the 51^3 Q1-hex sigma+mass system (N = 132651, nnz = 3442951, the
 paper's matrix size), b ~ U[-1, 1] (seed 0), x0 = 0, tol = 1e-10 on
 ||b - A x|| / ||b||.  One step is one full solve.  Prints ONE JSON line on
 stdout; progress goes to stderr.
+
+The other forms are measured against plain FP64 solves on the same GPU:
+mixed precision (51^3 and 128^3), 256 batched systems in one launch against
+a loop of single solves, 64 right-hand sides in one multi-RHS solve against
+64 single solves, and the learned warm start against x0 = 0 and two
+non-learned start vectors.
 """
 from __future__ import annotations
 
@@ -46,6 +52,34 @@ def solve_bytes(n, nnz, iters, checks, form="standard", vb=8, ib=4):
     return setup + iters * iter_bytes(n, nnz, form, vb, ib) + checks * (matrix + 3 * vb * n)
 
 
+# HBM bytes per iteration from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a
+# 512 MiB copy: fetch x2, write x1) for the 51^3 system at the default shape.
+MEASURED_TRAFFIC = {
+    ("standard", 132651, 3442951, 8, 512): 55.94e6,  # k_direction + k_update
+    ("single", 132651, 3442951, 8, 512): 56.18e6,    # k_sr_iter
+}
+
+
+def roofline(form, n, nnz, run):
+    """The iteration's kernels against the HBM roofline.
+
+    One CG iteration is the unit: k_direction + k_update (standard form) or
+    k_sr_iter (single-reduction form), launched in hipGraph chunks; its
+    duration is the event-timed device time of the solve over the iteration
+    count (setup and the final check are two products in 410 iterations).
+    """
+    per_iter_s = run["device_s"] / max(run["iters"], 1)
+    ib = iter_bytes(n, nnz, form)
+    launch = run["launch"]
+    traffic = MEASURED_TRAFFIC.get((form, n, nnz, launch["nnz_per_lane"], launch["block_size"]))
+    return {
+        "kernel": ("k_sr_iter" if form == "single" else "k_direction + k_update") + " (one CG iteration)",
+        "bound": "hbm", "achieved": ib / per_iter_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": ib / per_iter_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+        "bytes_per_launch": ib, "launch_s": per_iter_s,
+    }
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -57,6 +91,224 @@ def cpu_model():
     return platform.processor()
 
 
+
+def _timed(fn, reps):
+    """Median and mean wall time of fn() (device-synchronised) over reps calls, and the last result."""
+    import torch
+
+    ts, res = [], None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    return statistics.median(ts), statistics.mean(ts), res
+
+
+def bench_mixed(args, a51, b51, s51):
+    """FP32 inner / FP64 outer against the FP64 solve at 51^3 and 128^3."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1107_0538_amd import Solver
+
+    out = {}
+    for n in (51, 128):
+        if n == 51:
+            a, b = a51, b51
+        else:
+            log("building 128^3 system")
+            a, b = W.problem(128, 0)
+        bt = torch.as_tensor(b, device="cuda")
+        s64 = s51 if n == 51 else Solver(a)
+        smx = Solver(a, fp32_copy=True)
+        x64 = torch.zeros_like(bt)
+        xmx = torch.zeros_like(bt)
+
+        def f64():
+            x64.zero_()
+            return s64.cg_solve(bt, x64)
+
+        def fmx():
+            xmx.zero_()
+            return smx.cg_solve_mixed(bt, xmx)
+
+        reps = max(3, min(args.steps, 10))
+        f64(), fmx()
+        t64, _, i64 = _timed(f64, reps)
+        tmx, _, imx = _timed(fmx, reps)
+        err = float(torch.linalg.vector_norm(xmx - x64) / torch.linalg.vector_norm(x64))
+        out[f"{n}^3"] = {
+            "n": a.n, "nnz": a.nnz, "fp64_s": t64, "mixed_s": tmx, "speedup": t64 / tmx,
+            "fp64_iters": i64["iters"], "mixed_inner_iters": imx["iters"], "mixed_outer": imx["outer"],
+            "mixed_relres_true": imx["relres_true"], "fp64_relres_true": i64["relres_true"],
+            "mixed_vs_fp64_solution_relerr": err, "status": [i64["status"], imx["status"]],
+        }
+        log(f"mixed {n}^3: fp64 {t64 * 1e3:.2f} ms, mixed {tmx * 1e3:.2f} ms ({imx['outer']} outer, "
+            f"{imx['iters']} inner), err vs fp64 {err:.1e}")
+        del smx
+        if n != 51:
+            del s64
+    return out
+
+
+def bench_batched(args, *_):
+    """256 uneven systems in one persistent launch against a loop of 256 single FP64 solves."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1107_0538_amd import Batch, Solver
+
+    log("building 256 batched systems")
+    sys_ = W.batch_systems(256)
+    mats = [m for _, m, _ in sys_]
+    bt = Batch(mats)
+    b_cat = torch.as_tensor(np.concatenate([b for _, _, b in sys_]), device="cuda")
+    x_cat = torch.zeros_like(b_cat)
+
+    def fb():
+        x_cat.zero_()
+        return bt.cg_solve(b_cat, x_cat)
+
+    fb()
+    reps = max(3, min(args.steps, 10))
+    tb, _, infos = _timed(fb, reps)
+    assert all(i["status"] == 0 for i in infos)
+    log(f"batched: {tb * 1e3:.2f} ms for 256 systems; building 256 single contexts")
+    solvers = [Solver(m) for m in mats]
+    bs = [torch.as_tensor(b, device="cuda") for _, _, b in sys_]
+    xs = [torch.zeros_like(v) for v in bs]
+
+    def floop():
+        res = []
+        for sv, bv, xv in zip(solvers, bs, xs):
+            xv.zero_()
+            res.append(sv.cg_solve(bv, xv))
+        return res
+
+    floop()
+    tl, _, linfo = _timed(floop, 3)
+    diff = max(float(torch.linalg.vector_norm(x_cat[bt.offsets[k]:bt.offsets[k + 1]] - xs[k])
+                     / torch.linalg.vector_norm(xs[k])) for k in range(256))
+    teams, grid = bt.teams()
+    out = {"systems": 256, "rows_total": bt.n_total, "nnz_total": int(sum(m.nnz for m in mats)),
+           "batched_s": tb, "loop_s": tl, "speedup": tl / tb, "grid": grid,
+           "iters_min_max": [min(i["iters"] for i in infos), max(i["iters"] for i in infos)],
+           "loop_iters_total": int(sum(i["iters"] for i in linfo)),
+           "max_solution_relerr_vs_loop": diff}
+    log(f"batched {tb * 1e3:.2f} ms vs loop {tl * 1e3:.2f} ms ({tl / tb:.2f}x)")
+    del solvers
+    bt.close()
+    return out
+
+
+def bench_multi(args, a, b, s):
+    """64 right-hand sides in one multi-RHS solve against 64 single FP64 solves."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+
+    B = W.multi_rhs(a.n, 64)
+    Bd = torch.as_tensor(B, device="cuda")
+    cols = [torch.as_tensor(np.ascontiguousarray(B[:, j]), device="cuda") for j in range(64)]
+    X = torch.zeros_like(Bd)
+
+    def fm():
+        X.zero_()
+        return s.cg_solve_multi(Bd, X)
+
+    xs = [torch.zeros_like(c) for c in cols]
+
+    def fl():
+        res = []
+        for c, xv in zip(cols, xs):
+            xv.zero_()
+            res.append(s.cg_solve(c, xv))
+        return res
+
+    fm()
+    reps = max(3, min(args.steps, 5))
+    tm, _, minfo = _timed(fm, reps)
+    tl, _, linfo = _timed(fl, 2)
+    assert all(i["status"] == 0 for i in minfo) and all(i["status"] == 0 for i in linfo)
+    diff = max(float(torch.linalg.vector_norm(X[:, j] - xs[j]) / torch.linalg.vector_norm(xs[j])) for j in range(64))
+    out = {"rhs": 64, "multi_s": tm, "loop_s": tl, "speedup": tl / tm,
+           "multi_iters_max": max(i["iters"] for i in minfo), "loop_iters_max": max(i["iters"] for i in linfo),
+           "max_solution_relerr_vs_loop": diff, "fp32_refine": "not built"}
+    log(f"multi-RHS {tm * 1e3:.2f} ms vs 64 single solves {tl * 1e3:.2f} ms ({tl / tm:.2f}x)")
+    return out
+
+
+def bench_learned(args, a, b, s):
+    """POD + MLP warm start on the 2000-source family: held-out solve time and iterations."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1107_0538_amd import learned
+
+    fam = W.source_family(n=round(a.n ** (1 / 3)), count=2000, k=8, seed=3)
+    ws = learned.LearnedWarmStart(s, fam, n_pod=500, n_train=1500, modes=64, hidden=(256, 256), precision="bf16",
+                                  seed=0)
+    tol = args.learned_tol
+    ws.fit(epochs=args.learned_epochs, batch=256, tol=tol, log_every=50, log=lambda m: log(f"learned: {m}"))
+    log(f"learned: trained {ws.timings}, final loss {ws.loss_curve[-1]}")
+    dev = ws.Phi.device
+    n = a.n
+    held = np.arange(1500, 1500 + min(args.learned_eval, 500))
+    Bh = torch.as_tensor(np.ascontiguousarray(fam.rhs(held)), device=dev)  # (len, N)
+    theta = fam.theta()
+    # Non-learned start vectors, all on the device: constant-mode projection and POD-Galerkin.
+    ones = torch.ones((n, 1), dtype=torch.float64, device=dev)
+    a1 = s.spmv(ones.reshape(-1))
+    c1 = float(learned.dense_gram(ones, a1.reshape(n, 1)).item())
+    ones_c = ones / c1
+    APhi = s.spmm(ws.Phi.contiguous())
+    H = learned.dense_gram(ws.Phi, APhi).cpu().numpy()
+    Hinv = torch.as_tensor(np.linalg.inv(0.5 * (H + H.T)), device=dev)
+
+    def x0_zero(j, i):
+        return torch.zeros(n, dtype=torch.float64, device=dev)
+
+    def x0_mlp(j, i):
+        return ws.x0(theta[i:i + 1]).reshape(-1)
+
+    def x0_const(j, i):
+        return learned.dense_gemm(ones_c, learned.dense_gram(ones, Bh[j].reshape(n, 1))).reshape(-1)
+
+    def x0_galerkin(j, i):
+        y = learned.dense_gram(ws.Phi, Bh[j].reshape(n, 1))
+        return learned.dense_gemm(ws.Phi, learned.dense_gemm(Hinv, y)).reshape(-1)
+
+    out = {"tol": tol, "family": "8 Gaussian sources, centres U[0,1]^3 (theta = 24 numbers), widths U[.02,.1], "
+                     "amplitudes N(0,1) fixed; b = M f", "pod_modes": 64, "snapshots": 500, "train": 1500,
+           "held_out": len(held), "network": "24-256-256-64 bf16 (fp32 accumulation, fp32 master weights)",
+           "epochs": args.learned_epochs, "final_train_loss": ws.loss_curve[-1][1], **ws.timings,
+           "pod_energy_captured": float(ws.energy[:64].sum() / max(ws.energy.sum(), 1e-300))}
+    for name, fx in (("zero", x0_zero), ("mlp", x0_mlp), ("const", x0_const), ("galerkin", x0_galerkin)):
+        ts, its, r0 = [], [], []
+        for j, i in enumerate(held):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x = fx(j, i)
+            info = s.cg_solve(Bh[j], x, tol=tol)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            its.append(info["iters"])
+            assert info["status"] == 0, (name, i, info)
+            if j % 100 == 99:
+                log(f"learned x0={name}: {j + 1}/{len(held)} solves")
+        out[name] = {"mean_s": statistics.mean(ts), "median_s": statistics.median(ts),
+                     "mean_iters": statistics.mean(its), "median_iters": statistics.median(its)}
+        log(f"learned x0={name}: mean {statistics.mean(ts) * 1e3:.2f} ms, mean iters {statistics.mean(its):.1f}")
+    out["mlp_vs_zero_time_ratio"] = out["mlp"]["mean_s"] / out["zero"]["mean_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,7 +317,18 @@ def main():
     ap.add_argument("--n", type=int, default=51, help="grid edge (51 = the paper's N and NNZ)")
     ap.add_argument("--spmv-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch shape by timing (default: the library's default shape, the one profiled)")
+    ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--forms", default="mixed,batched,multi,learned",
+                    help="comma list of the forms measured against FP64 (empty: none)")
+    ap.add_argument("--learned-eval", type=int, default=500, help="held-out right-hand sides evaluated")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run plain device copies of this size (counter calibration under a profiler)")
+    ap.add_argument("--learned-epochs", type=int, default=400)
+    ap.add_argument("--learned-tol", type=float, default=1e-8,
+                    help="tolerance of the learned-form solves (1e-10 is below the attainable accuracy of "
+                         "this right-hand-side family in FP64)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs the whole system on a single MI355X "
@@ -83,11 +346,21 @@ def main():
     log(f"building {args.n}^3 system")
     a, b = W.problem(args.n, 0)
     n, nnz = a.n, a.nnz
-    s = Solver(a, autotune=not args.no_autotune)
+    s = Solver(a, autotune=args.autotune)
     cfg = s.config()
     log(f"config {cfg}")
     stream = torch.cuda.current_stream()
     bt = torch.as_tensor(b, device=dev)
+
+    if args.copy_probe_mb > 0:
+        # A plain copy of known size: HBM counters read under a profiler are
+        # scaled by what they report for it.
+        src = torch.ones(args.copy_probe_mb * 2 ** 20 // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # --- SpMV bandwidth (warm: repeated products; cold: 2 GB written between products)
     xv = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, n), device=dev)
@@ -118,7 +391,7 @@ def main():
     # --- time-to-solution, both forms of the iteration
     runs = {}
     for form in ("standard", "single"):
-        sf = s if form == "standard" else Solver(a, autotune=not args.no_autotune, form=form)
+        sf = s if form == "standard" else Solver(a, autotune=args.autotune, form=form)
         x = torch.zeros_like(bt)
         for _ in range(args.warmup):
             x.zero_()
@@ -176,13 +449,7 @@ def main():
             "cold_us_median": statistics.median(cold), "cold_gbs": sb / statistics.median(cold) / 1e3,
             "bytes": sb, "nnz_per_lane": cfg["nnz_per_lane"],
         },
-        "roofline": {
-            "kernel": ("whole solve: k_sr_iter per iteration" if best == "single"
-                       else "whole solve: k_direction + k_update per iteration") + ", hipGraph chunks",
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "bytes_per_launch": sbytes, "launch_s": kern_s,
-        },
+        "roofline": roofline(best, n, nnz, r),
         "paper_context": {"opencl_1gpu_tesla_t10_s": 0.659, "matlab_core2duo_s": 3.17,
                           "note": "different (unavailable) matrix and hardware; context only"},
     }
@@ -205,6 +472,17 @@ def main():
         }
         out["gpu_vs_oracle_solution_relerr"] = {
             f: float(np.linalg.norm(runs[f]["x"] - xo) / np.linalg.norm(xo)) for f in runs}
+    forms = [f for f in args.forms.split(",") if f]
+    if forms:
+        out["forms_vs_fp64"] = {}
+    for f in forms:
+        fn = {"mixed": bench_mixed, "batched": bench_batched, "multi": bench_multi, "learned": bench_learned}[f]
+        log(f"form {f}")
+        try:
+            out["forms_vs_fp64"][f] = fn(args, a, b, s)
+        except Exception as e:  # a failing side measurement must not hide the headline line
+            log(f"form {f} failed: {e!r}")
+            out["forms_vs_fp64"][f] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 

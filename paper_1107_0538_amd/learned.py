@@ -222,7 +222,7 @@ class LearnedWarmStart:
         self.net = None
 
     # snapshots: solve each training right-hand side with the multi-RHS solver
-    def snapshots(self, idx, tol=1e-10, block=64):
+    def snapshots(self, idx, tol=1e-10, block=64, maxit=0, log=None):
         """Device (N x len(idx)) block of solutions, and the per-solve infos."""
         torch = _torch()
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -232,7 +232,9 @@ class LearnedWarmStart:
         for j0 in range(0, len(idx), block):
             sel = idx[j0:j0 + block]
             B = torch.as_tensor(np.ascontiguousarray(self.family.rhs(sel).T), device=dev)
-            X, inf = self.solver.solve_multi(B, tol=tol)
+            X, inf = self.solver.solve_multi(B, tol=tol, maxit=maxit)
+            if log:
+                log(f"snapshots {j0 + len(sel)}/{len(idx)}: max iterations {max(i['iters'] for i in inf)}")
             bad = [j0 + j for j, i in enumerate(inf) if i["status"] != capi.CG_CONVERGED]
             if bad:
                 raise RuntimeError(f"snapshot solves did not converge for columns {bad[:8]}")
@@ -259,11 +261,12 @@ class LearnedWarmStart:
         """(columns of S) x k matrix of POD coefficients Phi' S, on the host."""
         return dense_gram(self.Phi, S).cpu().numpy().T.copy()
 
-    def fit(self, epochs=300, batch=256, lr=1e-3, log_every=0):
+    def fit(self, epochs=300, batch=256, lr=1e-3, log_every=0, tol=1e-10, maxit=0, log=None):
+        """Generate the snapshots (CG to tol), build the basis and train the network."""
         torch = _torch()
         dev = torch.device("cuda", torch.cuda.current_device())
         t0 = time.perf_counter()
-        S, infos = self.snapshots(np.arange(self.n_train))
+        S, infos = self.snapshots(np.arange(self.n_train), tol=tol, maxit=maxit, log=log)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         self.build_basis(S)
@@ -293,6 +296,8 @@ class LearnedWarmStart:
                                            want_loss=want)
                 if want:
                     self.loss_curve.append((ep, loss))
+                    if log:
+                        log(f"epoch {ep}: loss {loss:.3e}")
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         self._fold(dims)
