@@ -75,13 +75,12 @@ typedef struct {
     int32_t fp32_copy;     /* 1: also keep an FP32 copy of the values (mixed form)       */
     int32_t autotune;      /* 1: time launch shapes at create and keep the fastest       */
     int32_t nnz_per_lane;  /* 0 = default; else 4, 8 or 16: a product tile holds 64x that */
-    int32_t blocks_per_cu; /* 0 = default; persistent-grid workgroups per compute unit  */
+    int32_t blocks_per_cu; /* 0 = default; workgroups per compute unit of the grid      */
     int32_t history;       /* 1: record ||r_k|| / ||b|| for every iteration            */
     int32_t block_size;    /* 0 = default; else 256, 512 or 1024 threads per workgroup  */
     int32_t chunk;         /* 0 = default; CG iterations per launched hipGraph chunk    */
     int32_t form;          /* CG_FORM_STANDARD (default) or CG_FORM_SINGLE_REDUCTION    */
-    int32_t lanes_per_row; /* batched solver: lanes per CSR row, 8, 16 or 32 (0 = 16)  */
-    int32_t reserved[6];
+    int32_t reserved[7];   /* must be zero                                               */
 } cg_opts;
 
 /* Result of a solve. */
@@ -188,8 +187,15 @@ int cg_solve_multi(cg_ctx *ctx, const double *B, double *X, int32_t s, double to
  * host memory (mem = CG_MEM_HOST) and is validated like cg_create's input;
  * the systems are copied into one block-diagonal device CSR.  Each system is
  * solved by a team of workgroups sized in proportion to its expected work,
- * with cg_solve's algorithm and stopping rules.  opts->precond applies to
- * every system; opts->lanes_per_row picks the product's lanes per row.
+ * with cg_solve's algorithm and stopping rules; its rows are cut into
+ * product tiles and each workgroup of the team owns an equal run of them.
+ * opts->precond applies to every system; opts->nnz_per_lane picks the tile
+ * width (4, 8 or 16 nonzeros per lane, 0 = 8); opts->blocks_per_cu bounds the
+ * workgroups per compute unit (0 = three quarters of the occupancy limit;
+ * larger values are clamped to the limit, the most that can be co-resident).  Teams wait for each
+ * other at bounded barriers, so a device shared with other work while the
+ * batch runs can end the solve with CG_ETIMEOUT.  At most one system per
+ * co-resident workgroup slot (else CG_EINVAL).
  * Returns 0, CG_EINVAL, CG_EDIAG (some system lacks a positive diagonal),
  * CG_ENOMEM or CG_EHIP.
  */

@@ -32,7 +32,7 @@ class cg_opts(ctypes.Structure):
     _fields_ = [("precond", ctypes.c_int32), ("fp32_copy", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("nnz_per_lane", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("history", ctypes.c_int32), ("block_size", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("form", ctypes.c_int32), ("lanes_per_row", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class cg_info(ctypes.Structure):

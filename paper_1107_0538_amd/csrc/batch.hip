@@ -1,14 +1,15 @@
 // Batched Jacobi-PCG: many independent SPD systems in one persistent launch.
 //
 // The systems are concatenated into one block-diagonal CSR (global row and
-// column indices, int32).  System s is owned by a team of workgroups sized in
-// proportion to its expected work (nonzeros times an iteration count that
-// grows with the grid size); every team runs the full solve of the FP64
-// oracle's loop (pcg_team, residual replacement included) on its own rows,
-// meeting at its own grid barrier between steps -- a team of one workgroup
-// needs only __syncthreads.  The launch is captured in a hipGraph together
+// column indices, int32) and each system's rows are cut into product tiles
+// (tiles.hpp).  System s is owned by a team of workgroups sized in proportion
+// to its expected work (nonzeros times an iteration count that grows with the
+// grid size); member L of a team owns an equal run of the system's tiles.
+// Every team runs the full solve of the FP64 oracle's loop (pcg_team,
+// residual replacement included) on its own rows, meeting at its own grid
+// barrier between steps -- a team of one workgroup needs only __syncthreads.  The launch is captured in a hipGraph together
 // with the kernel that clears the barriers, so one graph launch solves the
-// whole batch.  All teams are co-resident (the grid stays within half the
+// whole batch.  All teams are co-resident (the grid stays within the
 // occupancy limit) and every barrier wait is bounded.
 #include <algorithm>
 #include <cmath>
@@ -36,7 +37,8 @@ struct BatchArgs {
     const int2* block_team;  // per workgroup: (system, member)
     const int* team_size;    // per system
     const int* part_off;     // per system: offset of its NSLOT * team_size partials
-    const int* blk_row;      // per workgroup: first global row; last entry = N_total
+    const int4* tiles;       // every system's product tiles, global rows and nonzeros
+    const int* tile_off;     // per system: first tile; last entry = total tiles
     const int* sys_rows;     // per system: number of rows
     GridBarrier* bar;        // per system
     double* part;
@@ -46,10 +48,11 @@ struct BatchArgs {
     long long limit;
 };
 
-template <int LPR, int BS>
+template <int NPL, int BS>
 __global__ __launch_bounds__(BS) void k_batch(BatchArgs a)
 {
     __shared__ double lds[(BS / kWave) * 4];
+    __shared__ double prod[BS * NPL];
     __shared__ int s_flag;
     const int2 bt = a.block_team[blockIdx.x];
     const int sys = bt.x;
@@ -61,10 +64,12 @@ __global__ __launch_bounds__(BS) void k_batch(BatchArgs a)
     t.gen = threadIdx.x == 0 ? barrier_gen(t.bar) : 0u;
     t.limit = a.limit;
     t.s_flag = &s_flag;
-    const int rs = a.blk_row[blockIdx.x], re = a.blk_row[blockIdx.x + 1];
+    const int t0 = a.tile_off[sys], nt = a.tile_off[sys + 1] - t0;
+    const TileMap tm{a.tiles + t0, nt, (nt + t.G - 1) / t.G};
     SysView<double> v{0, a.rowptr, a.col, a.val, a.dinv, a.b, a.x, a.r, a.z, a.p0, a.p1, a.q};
     const int maxit = a.maxit > 0 ? a.maxit : a.sys_rows[sys];
-    const int st = pcg_team<LPR, BS, double>(v, t, rs, re, a.tol, maxit, lds, a.info + sys, nullptr);
+    double* wprod = prod + (threadIdx.x / kWave) * (kWave * NPL);
+    const int st = pcg_team<NPL, BS, double>(v, t, tm, wprod, a.tol, maxit, lds, a.info + sys, nullptr);
     if (st == CG_ETIMEOUT && threadIdx.x == 0 && t.L == 0) a.info[sys].status = CG_ETIMEOUT;
 }
 
@@ -104,7 +109,7 @@ struct cg_batch {
     int nsys = 0;
     int64_t n_total = 0;
     int64_t nnz_total = 0;
-    int lpr = 16;
+    int npl = 8;
     int grid = 0;
     std::vector<int64_t> row_off;  // nsys + 1
     std::vector<int> team;         // team sizes
@@ -114,7 +119,8 @@ struct cg_batch {
     double* dinv = nullptr;
     double* vec = nullptr;  // b, x, r, z, p0, p1, q: 7 N_total
     int2* block_team = nullptr;
-    int* ints = nullptr;    // team_size, part_off, blk_row, sys_rows
+    int4* tiles = nullptr;
+    int* ints = nullptr;    // team_size, part_off, sys_rows, tile_off
     jpcg::GridBarrier* bar = nullptr;
     double* part = nullptr;
     jpcg::DevInfo* info = nullptr;
@@ -134,7 +140,8 @@ static void free_batch(cg_batch* b)
 {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    void* ptrs[] = {b->rowptr, b->col, b->val, b->dinv, b->vec, b->block_team, b->ints, b->bar, b->part, b->info};
+    void* ptrs[] = {b->rowptr, b->col, b->val, b->dinv, b->vec, b->block_team, b->tiles, b->ints, b->bar, b->part,
+                    b->info};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (b->hinfo) (void)hipHostFree(b->hinfo);
@@ -143,12 +150,12 @@ static void free_batch(cg_batch* b)
     delete b;
 }
 
-static const void* batch_kernel(int lpr)
+static const void* batch_kernel(int npl)
 {
-    switch (lpr) {
+    switch (npl) {
+        case 4: return (const void*)k_batch<4, kBatchBS>;
         case 8: return (const void*)k_batch<8, kBatchBS>;
         case 16: return (const void*)k_batch<16, kBatchBS>;
-        case 32: return (const void*)k_batch<32, kBatchBS>;
         default: return nullptr;
     }
 }
@@ -171,7 +178,7 @@ static void capture_batch(cg_batch* b, double tol, int maxit)
     JPCG_HIP(hipLaunchKernel((const void*)k_batch_clear, dim3(std::min(1024, (count + 255) / 256)), dim3(256), cargs,
                              0, cap));
     void* kargs[] = {&b->args};
-    JPCG_HIP(hipLaunchKernel(batch_kernel(b->lpr), dim3(b->grid), dim3(kBatchBS), kargs, 0, cap));
+    JPCG_HIP(hipLaunchKernel(batch_kernel(b->npl), dim3(b->grid), dim3(kBatchBS), kargs, 0, cap));
     JPCG_HIP(hipStreamEndCapture(cap, &graph));
     hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
@@ -201,8 +208,8 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         b = new cg_batch();
         b->stream = (hipStream_t)hip_stream;
         b->nsys = nsys;
-        b->lpr = o.lanes_per_row ? o.lanes_per_row : 16;
-        if (!batch_kernel(b->lpr)) {
+        b->npl = o.nnz_per_lane ? o.nnz_per_lane : 8;
+        if (!batch_kernel(b->npl)) {
             free_batch(b);
             return CG_EINVAL;
         }
@@ -251,15 +258,41 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         }
         rowptr[N] = (int)b->nnz_total;
 
+        // Product tiles of every system (global rows and nonzeros).
+        const int cap = kWave * b->npl;
+        std::vector<int4> tiles;
+        std::vector<int> tile_off(nsys + 1, 0);
+        for (int s = 0; s < nsys; ++s) {
+            const cg_csr& A = systems[s];
+            std::vector<int> local_rp(A.rowptr, A.rowptr + A.n + 1);
+            std::vector<int4> ts;
+            build_tiles(local_rp, cap, ts);
+            const int ro = (int)b->row_off[s], ko = (int)nnz_off[s];
+            for (const int4& t : ts) tiles.push_back(int4{t.x + ro, t.y + ro, t.z + ko, t.w + ko});
+            tile_off[s + 1] = (int)tiles.size();
+        }
+
         // Teams: workgroups per system in proportion to nnz times rows^(1/3)
-        // (CG iterations grow with the grid edge), within half the occupancy.
+        // (CG iterations grow with the grid edge), at most one per tile,
+        // within the co-resident capacity (three quarters of the occupancy
+        // limit unless opts->blocks_per_cu asks for another count per CU).  The product streams
+        // the whole batch's matrices from HBM every iteration, so it wants as
+        // many waves in flight as fit.
         int dev = 0, cus = 0, per_cu = 0, wall_khz = 0;
         JPCG_HIP(hipGetDevice(&dev));
         JPCG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         JPCG_HIP(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev));
-        JPCG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(b->lpr), kBatchBS, 0));
+        JPCG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(b->npl), kBatchBS, 0));
         b->limit = (long long)std::max(wall_khz, 1000) * 1000LL * 8;  // 8 s of device wall clock
-        const int capacity = std::max(nsys, std::max(1, per_cu * cus / 2));
+        const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, per_cu) : 0;
+        // A quarter of the slots stay free by default: filling every slot
+        // has left a team short of co-resident members (its barrier then
+        // times out) although the occupancy query allowed it.
+        const int capacity = std::max(nsys, std::max(1, bpc > 0 ? bpc * cus : per_cu * cus * 3 / 4));
+        if (nsys > per_cu * cus) {  // one workgroup per system must still be co-resident
+            free_batch(b);
+            return CG_EINVAL;
+        }
         std::vector<double> work(nsys);
         double total = 0.0;
         for (int s = 0; s < nsys; ++s) {
@@ -271,8 +304,8 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         int used = nsys;
         for (int s = 0; s < nsys; ++s) {
             const int want = std::max(1, (int)std::floor(work[s] / total * capacity));
-            const int rows_cap = std::max(1, systems[s].n / 64);  // at least 64 rows per workgroup
-            const int extra = std::min(want, rows_cap) - 1;
+            const int ntiles = std::max(1, tile_off[s + 1] - tile_off[s]);
+            const int extra = std::min(want, ntiles) - 1;
             if (used + extra <= capacity) {
                 b->team[s] += extra;
                 used += extra;
@@ -281,24 +314,17 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         b->grid = used;
         // Per-workgroup tables.
         std::vector<int2> block_team(used);
-        std::vector<int> blk_row(used + 1), team_size(nsys), part_off(nsys), sys_rows(nsys);
+        std::vector<int> team_size(nsys), part_off(nsys), sys_rows(nsys);
         int blk = 0, poff = 0;
         for (int s = 0; s < nsys; ++s) {
-            const cg_csr& A = systems[s];
             const int T = b->team[s];
             team_size[s] = T;
             part_off[s] = poff;
             poff += NSLOT * T;
-            sys_rows[s] = A.n;
-            std::vector<int> local_rp(A.rowptr, A.rowptr + A.n + 1), rows;
-            partition_rows(local_rp, T, rows);
-            for (int L = 0; L < T; ++L) {
-                block_team[blk] = int2{s, L};
-                blk_row[blk] = (int)b->row_off[s] + rows[L];
-                ++blk;
-            }
+            sys_rows[s] = systems[s].n;
+            for (int L = 0; L < T; ++L) block_team[blk++] = int2{s, L};
         }
-        blk_row[used] = N;
+        const int ntile_total = (int)tiles.size();
 
         // Device copies.
         JPCG_HIP(hipMalloc(&b->rowptr, sizeof(int) * (N + 1)));
@@ -307,7 +333,8 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         JPCG_HIP(hipMalloc(&b->dinv, sizeof(double) * N));
         JPCG_HIP(hipMalloc(&b->vec, sizeof(double) * 7 * (size_t)N));
         JPCG_HIP(hipMalloc(&b->block_team, sizeof(int2) * used));
-        JPCG_HIP(hipMalloc(&b->ints, sizeof(int) * (3 * (size_t)nsys + used + 1)));
+        JPCG_HIP(hipMalloc(&b->tiles, sizeof(int4) * std::max(ntile_total, 1)));
+        JPCG_HIP(hipMalloc(&b->ints, sizeof(int) * (4 * (size_t)nsys + 1)));
         JPCG_HIP(hipMalloc(&b->bar, sizeof(GridBarrier) * nsys));
         JPCG_HIP(hipMalloc(&b->part, sizeof(double) * std::max(poff, 1)));
         JPCG_HIP(hipMalloc(&b->info, sizeof(DevInfo) * nsys));
@@ -325,11 +352,13 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         int* d_team = b->ints;
         int* d_poff = d_team + nsys;
         int* d_rows = d_poff + nsys;
-        int* d_blk = d_rows + nsys;
+        int* d_toff = d_rows + nsys;
         JPCG_HIP(hipMemcpyAsync(d_team, team_size.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st));
         JPCG_HIP(hipMemcpyAsync(d_poff, part_off.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st));
         JPCG_HIP(hipMemcpyAsync(d_rows, sys_rows.data(), sizeof(int) * nsys, hipMemcpyHostToDevice, st));
-        JPCG_HIP(hipMemcpyAsync(d_blk, blk_row.data(), sizeof(int) * (used + 1), hipMemcpyHostToDevice, st));
+        JPCG_HIP(hipMemcpyAsync(d_toff, tile_off.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, st));
+        if (ntile_total > 0)
+            JPCG_HIP(hipMemcpyAsync(b->tiles, tiles.data(), sizeof(int4) * ntile_total, hipMemcpyHostToDevice, st));
         int* bad = nullptr;
         JPCG_HIP(hipMalloc(&bad, sizeof(int)));
         JPCG_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
@@ -360,7 +389,8 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         a.block_team = b->block_team;
         a.team_size = d_team;
         a.part_off = d_poff;
-        a.blk_row = d_blk;
+        a.tiles = b->tiles;
+        a.tile_off = d_toff;
         a.sys_rows = d_rows;
         a.bar = b->bar;
         a.part = b->part;

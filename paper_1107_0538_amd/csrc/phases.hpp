@@ -1,11 +1,11 @@
 // The steps of one Jacobi-PCG solve, as device functions over a block's rows.
 //
-// A "team" is a set of co-resident workgroups that owns one system: each
-// workgroup owns a contiguous row range [rs, re) (balanced by nonzeros on the
-// host) and the team meets at grid barriers between steps.  The single-system
-// solver runs one team made of the whole grid; the batched solver runs many
-// teams in one launch.  A team of one workgroup synchronises with
-// __syncthreads alone.
+// A "team" is a set of co-resident workgroups that owns one system: the
+// system's rows are cut into product tiles (tiles.hpp), workgroup L of the
+// team owns an equal run of tiles (so a contiguous row range), and the team
+// meets at grid barriers between steps.  The batched solver runs many teams
+// in one launch.  A team of one workgroup synchronises with __syncthreads
+// alone.
 //
 // Per iteration there are two team-wide reductions, so two barriers:
 //   step A   q = A p_new, p_new = z + beta p_old formed on the fly (the direction
@@ -19,7 +19,7 @@
 // precision form).  Dot products always accumulate in double.
 #pragma once
 
-#include "common.hpp"
+#include "tiles.hpp"
 
 namespace jpcg {
 
@@ -104,38 +104,55 @@ __device__ __forceinline__ float fma_t<float>(float a, float b, float c)
     return __builtin_fmaf(a, b, c);
 }
 
-// Step A: p_new = z + beta p_old (or z on the first step), q = A p_new.
-// Returns this thread's share of p_new' q.
-template <int LPR, int BS, typename T>
-__device__ __forceinline__ double step_a(const SysView<T>& s, int rs, int re, bool first, T beta,
+template <typename T>
+struct ZP {
+    T z, p;
+};
+
+template <typename T>
+struct BD {
+    T b, d;
+};
+
+// Rows [x, y) of workgroup L's tiles (empty when it owns none).
+__device__ __forceinline__ int2 tile_row_range(const TileMap& tm, int L)
+{
+    const int tb = L * tm.per_block, t1 = min(tb + tm.per_block, tm.T);
+    if (tb >= t1) return int2{0, 0};
+    return int2{tm.tiles[tb].x, tm.tiles[t1 - 1].y};
+}
+
+// Step A: p_new = z + beta p_old (or z on the first step), q = A p_new over the
+// workgroup's tiles, p_new formed on the fly in the gather.  Returns this
+// thread's share of p_new' q.
+template <int NPL, typename T>
+__device__ __forceinline__ double step_a(const SysView<T>& s, const TileMap& tm, int L, T* prod, bool first, T beta,
                                          const T* __restrict__ pold, T* __restrict__ pnew)
 {
-    const int lane = threadIdx.x & (LPR - 1);
-    const int grp = threadIdx.x / LPR;
-    constexpr int GPB = BS / LPR;
     const T* __restrict__ z = s.z;
+    T* __restrict__ q = s.q;
     double sig = 0.0;
-    for (int i0 = rs; i0 < re; i0 += GPB) {
-        const int i = i0 + grp;
-        T acc = T(0);
-        if (i < re) {
-            const int k1 = s.rowptr[i + 1];
-            if (first) {
-                for (int k = s.rowptr[i] + lane; k < k1; k += LPR) acc = fma_t(s.val[k], z[s.col[k]], acc);
-            } else {
-                for (int k = s.rowptr[i] + lane; k < k1; k += LPR) {
-                    const int j = s.col[k];
-                    acc = fma_t(s.val[k], fma_t(beta, pold[j], z[j]), acc);
-                }
-            }
-        }
-        acc = group_sum<LPR>(acc);
-        if (lane == 0 && i < re) {
-            const T pi = first ? z[i] : fma_t(beta, pold[i], z[i]);
-            pnew[i] = pi;
-            s.q[i] = acc;
-            sig += (double)pi * (double)acc;
-        }
+    if (first) {
+        tile_rows<NPL, T>(
+            s.rowptr, s.col, s.val, tm, L, prod, [&](int j) { return z[j]; }, Ident<T>{},
+            [&](int i) { return z[i]; },
+            [&](int i, T qi, T pi) {
+                pnew[i] = pi;
+                q[i] = qi;
+                sig += (double)pi * (double)qi;
+            },
+            NoPrologue{});
+    } else {
+        tile_rows<NPL, T>(
+            s.rowptr, s.col, s.val, tm, L, prod, [&](int j) { return ZP<T>{z[j], pold[j]}; },
+            [&](ZP<T> g) { return fma_t(beta, g.p, g.z); }, [&](int i) { return ZP<T>{z[i], pold[i]}; },
+            [&](int i, T qi, ZP<T> o) {
+                const T pi = fma_t(beta, o.p, o.z);
+                pnew[i] = pi;
+                q[i] = qi;
+                sig += (double)pi * (double)qi;
+            },
+            NoPrologue{});
     }
     return sig;
 }
@@ -157,36 +174,28 @@ __device__ __forceinline__ void step_b(const SysView<T>& s, int rs, int re, T al
     }
 }
 
-// Step R: rout = b - A x and, if zout, zout = M^-1 rout; shares of r'r, r'z, b'b.
-template <int LPR, int BS, typename T>
-__device__ __forceinline__ void step_r(const SysView<T>& s, int rs, int re, T* __restrict__ rout,
+// Step R: rout = b - A x and, if zout, zout = M^-1 rout over the workgroup's
+// tiles; shares of r'r, r'z, b'b.
+template <int NPL, typename T>
+__device__ __forceinline__ void step_r(const SysView<T>& s, const TileMap& tm, int L, T* prod, T* __restrict__ rout,
                                        T* __restrict__ zout, double& rr, double& rz, double& bb)
 {
-    const int lane = threadIdx.x & (LPR - 1);
-    const int grp = threadIdx.x / LPR;
-    constexpr int GPB = BS / LPR;
     const T* __restrict__ x = s.x;
-    for (int i0 = rs; i0 < re; i0 += GPB) {
-        const int i = i0 + grp;
-        T acc = T(0);
-        if (i < re) {
-            const int k1 = s.rowptr[i + 1];
-            for (int k = s.rowptr[i] + lane; k < k1; k += LPR) acc = fma_t(s.val[k], x[s.col[k]], acc);
-        }
-        acc = group_sum<LPR>(acc);
-        if (lane == 0 && i < re) {
-            const T bi = s.b[i];
-            const T ri = bi - acc;
+    tile_rows<NPL, T>(
+        s.rowptr, s.col, s.val, tm, L, prod, [&](int j) { return x[j]; }, Ident<T>{},
+        [&](int i) { return BD<T>{s.b[i], s.dinv[i]}; },
+        [&](int i, T ax, BD<T> o) {
+            const T ri = o.b - ax;
             rout[i] = ri;
             rr += (double)ri * (double)ri;
-            bb += (double)bi * (double)bi;
+            bb += (double)o.b * (double)o.b;
             if (zout) {
-                const T zi = s.dinv[i] * ri;
+                const T zi = o.d * ri;
                 zout[i] = zi;
                 rz += (double)ri * (double)zi;
             }
-        }
-    }
+        },
+        NoPrologue{});
 }
 
 // One full Jacobi-PCG solve of system s by team t, following the loop of the
@@ -194,17 +203,19 @@ __device__ __forceinline__ void step_r(const SysView<T>& s, int rs, int re, T* _
 // is taken on team-reduced scalars that are bitwise identical in every
 // workgroup, so all workgroups leave the loop together.  Returns the status;
 // workgroup 0 of the team writes *info (and hist[k] = ||r_k|| / ||b||).
-template <int LPR, int BS, typename T>
-__device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol, int maxit, double* lds,
-                        DevInfo* info, double* hist)
+template <int NPL, int BS, typename T>
+__device__ int pcg_team(const SysView<T>& s, Team& t, const TileMap& tm, T* prod, double tol, int maxit,
+                        double* lds, DevInfo* info, double* hist)
 {
     const bool writer = (t.L == 0 && threadIdx.x == 0);
+    const int2 rows = tile_row_range(tm, t.L);
+    const int rs = rows.x, re = rows.y;
     int status = CG_MAXIT, k = 0, repl = 0;
     double nb = 0.0, rr = 0.0, rrt = -1.0;
 
     {   // r0 = b - A x0, z0 = M^-1 r0, ||b||^2, ||r0||^2, r0'z0
         double v[3] = {0.0, 0.0, 0.0};
-        step_r<LPR, BS, T>(s, rs, re, s.r, s.z, v[0], v[1], v[2]);
+        step_r<NPL, T>(s, tm, t.L, prod, s.r, s.z, v[0], v[1], v[2]);
         block_partials<BS, 3>(v, lds, t.slot(SLOT_SETUP), t.L);
     }
     if (!t.sync()) return CG_ETIMEOUT;
@@ -243,7 +254,7 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol
         const T* pold = (k & 1) ? s.p1 : s.p0;
         T* pnew = (k & 1) ? s.p0 : s.p1;
         {
-            double v[1] = {step_a<LPR, BS, T>(s, rs, re, k == 0, (T)beta, pold, pnew)};
+            double v[1] = {step_a<NPL, T>(s, tm, t.L, prod, k == 0, (T)beta, pold, pnew)};
             block_partials<BS, 1>(v, lds, t.slot(SLOT_SIG), t.L);
         }
         if (!t.sync()) return CG_ETIMEOUT;
@@ -277,7 +288,7 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol
             // Continue-condition met on the recurrence: confirm on b - A x.
             {
                 double v[2] = {0.0, 0.0}, unused = 0.0;
-                step_r<LPR, BS, T>(s, rs, re, s.r, s.z, v[0], v[1], unused);
+                step_r<NPL, T>(s, tm, t.L, prod, s.r, s.z, v[0], v[1], unused);
                 block_partials<BS, 2>(v, lds, t.slot(SLOT_CHECK), t.L);
             }
             if (!t.sync()) return CG_ETIMEOUT;
@@ -301,7 +312,7 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, int rs, int re, double tol
 
     if (rrt < 0.0) {  // report the true residual of the returned x
         double v[1] = {0.0}, unused0 = 0.0, unused1 = 0.0;
-        step_r<LPR, BS, T>(s, rs, re, s.q, (T*)nullptr, v[0], unused0, unused1);
+        step_r<NPL, T>(s, tm, t.L, prod, s.q, (T*)nullptr, v[0], unused0, unused1);
         block_partials<BS, 1>(v, lds, t.slot(SLOT_CHECK), t.L);
         if (!t.sync()) return CG_ETIMEOUT;
         double g[1];

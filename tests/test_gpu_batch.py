@@ -37,12 +37,12 @@ def check_system(a, b, x, info):
     assert oracle.relres(a, b, x) <= TOL_RECOMPUTED
 
 
-@pytest.mark.parametrize("lpr", [8, 16, 32])
-def test_small_batch_parity(cuda, lpr):
+@pytest.mark.parametrize("npl,bpc", [(4, 0), (8, 0), (16, 0), (8, 1)])
+def test_small_batch_parity(cuda, npl, bpc):
     from paper_1107_0538_amd import Batch
 
     sys = small_batch()
-    bt = Batch([a for a, _ in sys], lanes_per_row=lpr)
+    bt = Batch([a for a, _ in sys], nnz_per_lane=npl, blocks_per_cu=bpc)
     b_cat = np.concatenate([b for _, b in sys])
     x, infos = bt.solve(_t(b_cat, cuda))
     x = x.cpu().numpy()
