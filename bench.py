@@ -53,10 +53,11 @@ def solve_bytes(n, nnz, iters, checks, form="standard", vb=8, ib=4):
 
 
 # HBM bytes per iteration from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a
-# 512 MiB copy: fetch x2, write x1) for the 51^3 system at the default shape.
+# 512 MiB copy: fetch x2, write x1) for the 51^3 system, keyed by form and
+# launch shape (nonzeros per lane, block size).
 MEASURED_TRAFFIC = {
-    ("standard", 132651, 3442951, 8, 512): 55.94e6,  # k_direction + k_update
-    ("single", 132651, 3442951, 8, 512): 56.18e6,    # k_sr_iter
+    ("standard", 132651, 3442951, 16, 512): 55.73e6,  # k_direction + k_update
+    ("single", 132651, 3442951, 8, 512): 56.39e6,     # k_sr_iter
 }
 
 

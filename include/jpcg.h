@@ -74,7 +74,8 @@ typedef struct {
     int32_t precond;       /* CG_PRECOND_JACOBI (default) or CG_PRECOND_NONE (M = I)    */
     int32_t fp32_copy;     /* 1: also keep an FP32 copy of the values (mixed form)       */
     int32_t autotune;      /* 1: time launch shapes at create and keep the fastest       */
-    int32_t nnz_per_lane;  /* 0 = default; else 4, 8 or 16: a product tile holds 64x that */
+    int32_t nnz_per_lane;  /* 4, 8 or 16: a product tile holds 64x that; 0 = default  */
+                           /* (16, or 8 for the single-reduction form)                 */
     int32_t blocks_per_cu; /* 0 = default; workgroups per compute unit of the grid      */
     int32_t history;       /* 1: record ||r_k|| / ||b|| for every iteration            */
     int32_t block_size;    /* 0 = default; else 256, 512 or 1024 threads per workgroup  */

@@ -105,10 +105,14 @@ __device__ __forceinline__ void wave_grid_sum(const double* __restrict__ part, i
 // ---------------------------------------------------------------------------
 // Grid barrier for co-resident (cooperatively launched) grids.
 //
-// Sense by generation: each arriving block adds one to `count`; the last one
-// resets `count` and advances `gen`; the others spin on `gen`.  Thread 0 of a
-// block fences at agent scope before arriving (publishing the block's writes
-// to all XCDs) and after leaving (so later loads observe other blocks'
+// Sense by generation: each arriving block adds one to `count`, which only
+// grows during a launch (it is cleared before the launch); the block whose
+// arrival completes generation g (count reaching (g + 1) * nblocks) advances
+// `gen`, and the others spin on `gen`.  Never resetting `count` matters: a
+// reset store and the `gen` store may become visible in either order, and a
+// fast block's arrival at the next barrier could then be wiped out.  Thread 0
+// of a block fences at agent scope before arriving (publishing the block's
+// writes to all XCDs) and after leaving (so later loads observe other blocks'
 // writes).  Every wait is bounded by a wall-clock limit: on expiry the block
 // raises `abort`, and every waiter that sees `abort` leaves, so all waves
 // exit even if a block never arrives.
@@ -140,11 +144,10 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier* gb, unsigned nblocks, 
     if (threadIdx.x == 0) {
         int ok = 1;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        unsigned prev = __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == nblocks - 1) {
+        const unsigned prev = __hip_atomic_fetch_add(&gb->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == (gen + 1) * nblocks - 1) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-            __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&gb->gen, gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&gb->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const long long t0 = wall_clock64();
             while (__hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
