@@ -8,16 +8,21 @@
 // multiply and add, so spmm's column j equals the sequential CSR product.
 //
 // Per iteration (parity P), all captured in hipGraph chunks:
-//   k_mr_direction  p_j = z_j + beta_j p_j (on the fly), q = A p, partials of p_j'q_j
-//   k_mr_scalars    one workgroup: sigma_j, alpha_j, breakdown per column
+//   k_mr_pnew       p_j = z_j + beta_j p_j (active), z_j (first step) or p_j
+//                   carried forward (frozen), elementwise
+//   k_mr_direction  q = A p, partials of p_j'q_j (one gathered row of p per
+//                   nonzero)
+//   k_mr_scalars    one workgroup per column: sigma_j, alpha_j, breakdown
 //   k_mr_update     x += alpha p, r -= alpha q, z = M^-1 r, partials of r'z, r'r
-//   k_mr_scalars    one workgroup: continue-condition, breakdown, limit, beta
+//   k_mr_scalars    one workgroup per column: continue-condition, breakdown,
+//                   limit, beta
 // A column whose recurrence residual passes is frozen (its p is carried
 // forward unchanged) and waits; when no column is active the host runs one
 // true-residual check for all waiting columns, exactly the oracle's check,
-// and resumes replaced ones.  Reductions of per-workgroup partials run in a
-// separate one-workgroup kernel: a redundant per-wave reduction of 64 columns
-// would multiply cache traffic by the grid size.
+// and resumes replaced ones.  Each column's per-workgroup partials are
+// reduced by that column's own workgroup of the scalar kernel, in a fixed
+// order; whether any column is still active is read from the 64 statuses by
+// every kernel that needs it.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -40,10 +45,8 @@ enum ColStatus : int {
 constexpr int kCols = 64;
 
 struct MrState {
-    int stop;          // no column active
-    int any_pending;
     int kk;            // iterations completed (the next one is kk + 1, parity (kk + 1) & 1)
-    int pad;
+    int pad[3];
     int status[kCols];
     int iters[kCols];
     int repl[kCols];
@@ -126,6 +129,14 @@ __device__ __forceinline__ T mr_row(const int* __restrict__ rowptr, const int* _
     return acc;
 }
 
+// True in every thread if some column is active (each wave reads the 64
+// statuses once).
+__device__ __forceinline__ bool mr_any_active(const MrState* st)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    return __ballot(st->status[lane] == COL_ACTIVE) != 0ull;
+}
+
 // Residual R = B - A X with Z = M^-1 R and partials (r'r, r'z, b'b) per column.
 // mode 0: setup (every column; clears both P buffers), 1: check (only pending
 // columns are rewritten), 2: report (nothing is written but the partials).
@@ -164,39 +175,53 @@ __global__ __launch_bounds__(BS) void k_mr_residual(MrArgs<T> a, int mode)
     mr_block_partials<BS, 3>(v, a.part, L);
 }
 
-// q = A p_new with p_new = z + beta p_old (active), z (first step) or p_old
-// (frozen: carried forward); partials of p_new'q.
+// p_new = z + beta p_old (active), z (first step) or p_old (frozen: carried
+// forward), elementwise over the block's rows.
 template <int BS, typename T>
-__global__ __launch_bounds__(BS) void k_mr_direction(MrArgs<T> a, int P)
+__global__ __launch_bounds__(BS) void k_mr_pnew(MrArgs<T> a, int P)
 {
     const MrState* st = a.st;
-    if (st->stop) return;
+    if (!mr_any_active(st)) return;
     const int L = mr_logical(a.G);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int rs = min(L * a.rows_per_block, a.n), re = min(rs + a.rows_per_block, a.n);
     const int s = a.s;
-    const bool used = lane < s;
-    const int cl = used ? lane : 0;
-    const int status = used ? st->status[lane] : COL_UNUSED;
+    if (lane >= s) return;
+    const int status = st->status[lane];
     const bool active = status == COL_ACTIVE;
     const bool first = active && st->first[lane];
     const T beta = (T)st->beta[lane];
     const T* __restrict__ Z = a.Z;
     const T* __restrict__ pold = a.P[P ^ 1];
     T* __restrict__ pnew = a.P[P];
-    auto pval = [&](size_t o) -> T {
+    for (int i = rs + w; i < re; i += BS / kWave) {
+        const size_t o = (size_t)i * s + lane;
         const T po = pold[o];
-        return active ? (first ? Z[o] : fma_t(beta, po, Z[o])) : po;
-    };
+        pnew[o] = active ? (first ? Z[o] : fma_t(beta, po, Z[o])) : po;
+    }
+}
+
+// q = A p_new (p_new from k_mr_pnew); partials of p_new'q for active columns.
+template <int BS, typename T>
+__global__ __launch_bounds__(BS) void k_mr_direction(MrArgs<T> a, int P)
+{
+    const MrState* st = a.st;
+    if (!mr_any_active(st)) return;
+    const int L = mr_logical(a.G);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int rs = min(L * a.rows_per_block, a.n), re = min(rs + a.rows_per_block, a.n);
+    const int s = a.s;
+    const bool used = lane < s;
+    const int cl = used ? lane : 0;
+    const bool active = used && st->status[lane] == COL_ACTIVE;
+    const T* __restrict__ pnew = a.P[P];
     double v[1] = {0.0};
     for (int i = rs + w; i < re; i += BS / kWave) {
-        const T qi = mr_row<T>(a.rowptr, a.col, a.val, i, [&](int j) { return pval((size_t)j * s + cl); });
+        const T qi = mr_row<T>(a.rowptr, a.col, a.val, i, [&](int j) { return pnew[(size_t)j * s + cl]; });
         const size_t o = (size_t)i * s + cl;
-        const T pi = pval(o);
         if (used) {
-            pnew[o] = pi;
             a.Q[o] = qi;
-            if (active) v[0] += (double)pi * (double)qi;
+            if (active) v[0] += (double)pnew[o] * (double)qi;
         }
     }
     mr_block_partials<BS, 1>(v, a.part, L);
@@ -206,13 +231,14 @@ __global__ __launch_bounds__(BS) void k_mr_direction(MrArgs<T> a, int P)
 template <int BS, typename T>
 __global__ __launch_bounds__(BS) void k_mr_update(MrArgs<T> a, int P)
 {
-    const MrState* st = a.st;
-    if (st->stop) return;
+    MrState* st = a.st;
+    if (!mr_any_active(st)) return;
     const int L = mr_logical(a.G);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int rs = min(L * a.rows_per_block, a.n), re = min(rs + a.rows_per_block, a.n);
     const int s = a.s;
     const bool active = lane < s && st->status[lane] == COL_ACTIVE;
+    if (L == 0 && threadIdx.x == 0) st->kk += 1;  // this iteration is being done
     const T alpha = (T)st->alpha[lane < s ? lane : 0];
     const T* __restrict__ p = a.P[P];
     double v[2] = {0.0, 0.0};
@@ -231,137 +257,111 @@ __global__ __launch_bounds__(BS) void k_mr_update(MrArgs<T> a, int P)
     mr_block_partials<BS, 2>(v, a.part, L);
 }
 
-// One workgroup of 64 * NW threads reduces the G partials of K quantities per
-// column: wave w takes workgroups w, w + NW, ...; then waves combine in order.
-template <int NW, int K>
-__device__ __forceinline__ void mr_reduce(const double* part, int G, double (&out)[K])
-{
-    __shared__ double lds[NW][K][kWave];
-    const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    double acc[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int g = w; g < G; g += NW) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += part[((size_t)g * K + k) * kWave + lane];
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) lds[w][k][lane] = acc[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double t = 0.0;
-#pragma unroll
-        for (int j = 0; j < NW; ++j) t += lds[j][k][lane];
-        out[k] = t;
-    }
-}
-
 enum MrPhase : int { MR_SETUP = 0, MR_SIGMA = 1, MR_ITER = 2, MR_CHECK = 3, MR_REPORT = 4 };
 
-// The per-column scalar steps, one workgroup of 4 waves; wave 0 lane j owns
-// column j's state.
+// Column j's sums of the G per-workgroup partials of K quantities, in a fixed
+// order; the totals are returned in every thread.
+template <int BS, int K>
+__device__ __forceinline__ void mr_column_sum(const double* part, int G, int j, double (&out)[K], double* lds)
+{
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = 0.0;
+    for (int g = threadIdx.x; g < G; g += BS) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] += part[((size_t)g * K + k) * kWave + j];
+    }
+    block_sum<BS, K>(out, lds);
+}
+
+// The per-column scalar steps: workgroup j owns column j's state.
 template <typename T>
 __global__ __launch_bounds__(256) void k_mr_scalars(MrArgs<T> a, int phase)
 {
+    __shared__ double lds[(256 / kWave) * 3];
     MrState* st = a.st;
-    if ((phase == MR_SIGMA || phase == MR_ITER) && st->stop) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    double g[3];
+    const int j = blockIdx.x;
+    if (phase == MR_SETUP && j == 0 && threadIdx.x == 0) st->kk = 0;
+    if (j >= a.s) {
+        if (phase == MR_SETUP && threadIdx.x == 0) st->status[j] = COL_UNUSED;
+        return;
+    }
+    int status = st->status[j];
+    if ((phase == MR_SIGMA || phase == MR_ITER) && status != COL_ACTIVE) return;
+    if (phase == MR_CHECK && status != COL_PENDING) return;
+    double g[3] = {0.0, 0.0, 0.0};
     if (phase == MR_SIGMA) {
         double t[1];
-        mr_reduce<4, 1>(a.part, a.G, t);
+        mr_column_sum<256, 1>(a.part, a.G, j, t, lds);
         g[0] = t[0];
     } else if (phase == MR_ITER) {
         double t[2];
-        mr_reduce<4, 2>(a.part, a.G, t);
+        mr_column_sum<256, 2>(a.part, a.G, j, t, lds);
         g[0] = t[0];
         g[1] = t[1];
     } else {
-        mr_reduce<4, 3>(a.part, a.G, g);
+        mr_column_sum<256, 3>(a.part, a.G, j, g, lds);
     }
-    if (threadIdx.x >= kWave) return;
-    const int j = lane;
-    int status = j < a.s ? st->status[j] : COL_UNUSED;
+    if (threadIdx.x != 0) return;
     if (phase == MR_SETUP) {
         // g = (r'r, r'z, b'b) of r0
-        if (j == 0) st->kk = 0;
         st->repl[j] = 0;
         st->iters[j] = 0;
         st->first[j] = 1;
         st->beta[j] = 0.0;
         st->alpha[j] = 0.0;
-        if (j >= a.s) {
-            status = COL_UNUSED;
+        const double nb = sqrt(g[2]);
+        st->nb[j] = nb;
+        st->thr[j] = a.tol * nb;
+        st->rr[j] = g[0];
+        st->rho[j] = g[1];
+        st->rr_true[j] = -1.0;
+        if (nb == 0.0) {
+            status = COL_ZERO;
+            st->rr_true[j] = 0.0;
+        } else if (sqrt(g[0]) <= a.tol * nb) {
+            status = COL_CONVERGED;
+            st->rr_true[j] = g[0];
         } else {
-            const double nb = sqrt(g[2]);
-            st->nb[j] = nb;
-            st->thr[j] = a.tol * nb;
-            st->rr[j] = g[0];
-            st->rho[j] = g[1];
-            st->rr_true[j] = -1.0;
-            if (nb == 0.0) {
-                status = COL_ZERO;
-                st->rr_true[j] = 0.0;
-            } else if (sqrt(g[0]) <= a.tol * nb) {
-                status = COL_CONVERGED;
-                st->rr_true[j] = g[0];
-            } else {
-                status = COL_ACTIVE;
-            }
+            status = COL_ACTIVE;
         }
     } else if (phase == MR_SIGMA) {
-        if (status == COL_ACTIVE) {
-            const double sigma = g[0];
-            if (!(sigma > 0.0) || !isfinite(sigma)) status = COL_BREAKDOWN;
-            else st->alpha[j] = st->rho[j] / sigma;
-        }
+        const double sigma = g[0];
+        if (!(sigma > 0.0) || !isfinite(sigma)) status = COL_BREAKDOWN;
+        else st->alpha[j] = st->rho[j] / sigma;
     } else if (phase == MR_ITER) {
         // g = (r'z, r'r) after the update: the oracle's order of tests.
-        if (j == 0) st->kk += 1;
-        if (status == COL_ACTIVE) {
-            st->iters[j] += 1;
-            st->first[j] = 0;
-            st->rr[j] = g[1];
-            if (sqrt(g[1]) <= st->thr[j]) {
-                status = COL_PENDING;
-            } else if (!(g[0] > 0.0) || !isfinite(g[0])) {
-                status = COL_BREAKDOWN;
-            } else if (st->iters[j] >= a.maxit) {
-                status = COL_MAXIT;
-            } else {
-                st->beta[j] = g[0] / st->rho[j];
-                st->rho[j] = g[0];
-            }
+        st->iters[j] += 1;
+        st->first[j] = 0;
+        st->rr[j] = g[1];
+        if (sqrt(g[1]) <= st->thr[j]) {
+            status = COL_PENDING;
+        } else if (!(g[0] > 0.0) || !isfinite(g[0])) {
+            status = COL_BREAKDOWN;
+        } else if (st->iters[j] >= a.maxit) {
+            status = COL_MAXIT;
+        } else {
+            st->beta[j] = g[0] / st->rho[j];
+            st->rho[j] = g[0];
         }
     } else if (phase == MR_CHECK) {
         // g = (r'r, r'z, b'b) of the true residual; r, z were replaced for pending columns.
-        if (status == COL_PENDING) {
-            if (sqrt(g[0]) <= st->thr[j]) {
-                status = COL_CONVERGED;
-                st->rr_true[j] = g[0];
-            } else if (!(g[1] > 0.0) || !isfinite(g[1])) {
-                status = COL_BREAKDOWN;
-            } else if (st->iters[j] >= a.maxit) {
-                status = COL_MAXIT;
-            } else {
-                status = COL_ACTIVE;
-                st->repl[j] += 1;
-                st->beta[j] = g[1] / st->rho[j];
-                st->rho[j] = g[1];
-            }
+        if (sqrt(g[0]) <= st->thr[j]) {
+            status = COL_CONVERGED;
+            st->rr_true[j] = g[0];
+        } else if (!(g[1] > 0.0) || !isfinite(g[1])) {
+            status = COL_BREAKDOWN;
+        } else if (st->iters[j] >= a.maxit) {
+            status = COL_MAXIT;
+        } else {
+            status = COL_ACTIVE;
+            st->repl[j] += 1;
+            st->beta[j] = g[1] / st->rho[j];
+            st->rho[j] = g[1];
         }
     } else {  // MR_REPORT: true residual of the returned x for every column
-        if (j < a.s && status != COL_ZERO) st->rr_true[j] = g[0];
+        if (status != COL_ZERO) st->rr_true[j] = g[0];
     }
     st->status[j] = status;
-    // Flags from wave 0: any column active, any pending.
-    const unsigned long long act = __ballot(status == COL_ACTIVE);
-    const unsigned long long pen = __ballot(status == COL_PENDING);
-    if (j == 0) {
-        st->stop = act == 0ull;
-        st->any_pending = pen != 0ull;
-    }
 }
 
 // x_j = 0 for columns with b_j = 0.
@@ -486,12 +486,13 @@ static void capture_multi(cg_multi* m)
         for (int it = 0; it < m->chunk; ++it) {
             int P = (par + it) & 1, ph_sig = MR_SIGMA, ph_it = MR_ITER;
             void* a0[] = {&m->args, &P};
+            mr_launch((const void*)k_mr_pnew<kMrBS, double>, m->G, kMrBS, cap, a0);
             mr_launch((const void*)k_mr_direction<kMrBS, double>, m->G, kMrBS, cap, a0);
             void* a1[] = {&m->args, &ph_sig};
-            mr_launch((const void*)k_mr_scalars<double>, 1, 256, cap, a1);
+            mr_launch((const void*)k_mr_scalars<double>, kCols, 256, cap, a1);
             mr_launch((const void*)k_mr_update<kMrBS, double>, m->G, kMrBS, cap, a0);
             void* a2[] = {&m->args, &ph_it};
-            mr_launch((const void*)k_mr_scalars<double>, 1, 256, cap, a2);
+            mr_launch((const void*)k_mr_scalars<double>, kCols, 256, cap, a2);
         }
         JPCG_HIP(hipStreamEndCapture(cap, &graph));
         hipError_t e = hipGraphInstantiate(&m->exec[par], graph, nullptr, nullptr, 0);
@@ -563,7 +564,7 @@ int cg_solve_multi(cg_ctx* c, const double* B, double* X, int32_t s, double tol,
         void* ra[] = {&m->args, &mode};
         mr_launch((const void*)k_mr_residual<kMrBS, double>, m->G, kMrBS, st, ra);
         void* sa[] = {&m->args, &ph};
-        mr_launch((const void*)k_mr_scalars<double>, 1, 256, st, sa);
+        mr_launch((const void*)k_mr_scalars<double>, kCols, 256, st, sa);
         void* za[] = {&m->args};
         mr_launch((const void*)k_mr_zero_cols<double>, 256, 256, st, za);
         int next = 1;
@@ -571,16 +572,21 @@ int cg_solve_multi(cg_ctx* c, const double* B, double* X, int32_t s, double tol,
         long long launched = 0;
         while (true) {
             MrState h = mr_read(c, m);
-            // Iterations after the stop flag was raised returned early, so the
+            // Iterations after the last column stopped returned early, so the
             // next iteration's parity comes from the device's count, not from
             // the number of iterations launched.
             next = h.kk + 1;
-            if (h.stop) {
-                if (!h.any_pending) break;
+            bool active = false, pending = false;
+            for (int j = 0; j < s; ++j) {
+                active = active || h.status[j] == COL_ACTIVE;
+                pending = pending || h.status[j] == COL_PENDING;
+            }
+            if (!active) {
+                if (!pending) break;
                 mode = 1;
                 ph = MR_CHECK;
                 mr_launch((const void*)k_mr_residual<kMrBS, double>, m->G, kMrBS, st, ra);
-                mr_launch((const void*)k_mr_scalars<double>, 1, 256, st, sa);
+                mr_launch((const void*)k_mr_scalars<double>, kCols, 256, st, sa);
                 continue;
             }
             if (launched > guard) throw HipError{hipErrorUnknown, "multi-RHS solver did not stop"};
@@ -594,7 +600,7 @@ int cg_solve_multi(cg_ctx* c, const double* B, double* X, int32_t s, double tol,
         mode = 2;
         ph = MR_REPORT;
         mr_launch((const void*)k_mr_residual<kMrBS, double>, m->G, kMrBS, st, ra);
-        mr_launch((const void*)k_mr_scalars<double>, 1, 256, st, sa);
+        mr_launch((const void*)k_mr_scalars<double>, kCols, 256, st, sa);
         JPCG_HIP(hipMemcpyAsync(X, m->args.X, nb, hipMemcpyDeviceToDevice, st));
         JPCG_HIP(hipEventRecord(c->ev1, st));
         const MrState h = mr_read(c, m);
