@@ -7,6 +7,11 @@
 
 #include "phases.hpp"
 
+namespace jpcg {
+// Zero entries after the last nonzero of the context's col and val arrays.
+constexpr int kCsrPad = 16;
+}  // namespace jpcg
+
 struct cg_ctx {
     int device = 0;
     hipStream_t stream = nullptr;

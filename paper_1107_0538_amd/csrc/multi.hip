@@ -112,20 +112,29 @@ __device__ __forceinline__ T mr_row(const int* __restrict__ rowptr, const int* _
                                     const T* __restrict__ val, int i, Gather gather)
 {
 #pragma clang fp contract(off)
-    const int k0 = rowptr[i], k1 = rowptr[i + 1];
+    // Batches of 16 nonzeros: the (wave-uniform) indices and values are
+    // loaded, then all 16 gathers are in flight together; the tail batch
+    // reads past the row's end (into the next row or the arrays' zero pad of
+    // kCsrPad entries) and skips those slots, so a 27-entry row takes two
+    // gather round trips.
+    constexpr int B = 16;
+    static_assert(B <= kCsrPad, "batch reads must stay within the padded arrays");
+    // The row is the same in every lane: make that explicit so that the
+    // row's indices and values come through the scalar cache.
+    i = __builtin_amdgcn_readfirstlane(i);
+    const int k0 = __builtin_amdgcn_readfirstlane(rowptr[i]), k1 = __builtin_amdgcn_readfirstlane(rowptr[i + 1]);
     T acc = T(0);
-    int k = k0;
-    for (; k + 8 <= k1; k += 8) {
-        T v[8], g[8];
+    for (int k = k0; k < k1; k += B) {
+        T v[B], g[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < B; ++u) {
             v[u] = val[k + u];
             g[u] = gather(col[k + u]);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc = acc + v[u] * g[u];
+        for (int u = 0; u < B; ++u)
+            if (k + u < k1) acc = acc + v[u] * g[u];
     }
-    for (; k < k1; ++k) acc = acc + val[k] * gather(col[k]);
     return acc;
 }
 

@@ -798,8 +798,12 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
         }
 
         JPCG_HIP(hipMalloc(&c->rowptr, sizeof(int) * (n + 1)));
-        JPCG_HIP(hipMalloc(&c->col, sizeof(int) * std::max<int64_t>(nnz, 1)));
-        JPCG_HIP(hipMalloc(&c->val, sizeof(double) * std::max<int64_t>(nnz, 1)));
+        // kCsrPad zero entries after the last nonzero: batched loads of a
+        // row's entries may run past its end (the extra slots are ignored).
+        JPCG_HIP(hipMalloc(&c->col, sizeof(int) * (nnz + kCsrPad)));
+        JPCG_HIP(hipMalloc(&c->val, sizeof(double) * (nnz + kCsrPad)));
+        JPCG_HIP(hipMemsetAsync(c->col + nnz, 0, sizeof(int) * kCsrPad, c->stream));
+        JPCG_HIP(hipMemsetAsync(c->val + nnz, 0, sizeof(double) * kCsrPad, c->stream));
         JPCG_HIP(hipMalloc(&c->dinv, sizeof(double) * n));
         JPCG_HIP(hipMalloc(&c->work[0], sizeof(double) * (size_t)n * cg_ctx::kWorkVecs));
         for (int v = 1; v < cg_ctx::kWorkVecs; ++v) c->work[v] = c->work[0] + (size_t)v * n;
