@@ -74,6 +74,8 @@ typedef struct {
     int32_t precond;       /* CG_PRECOND_JACOBI (default) or CG_PRECOND_NONE (M = I)    */
     int32_t fp32_copy;     /* 1: also keep an FP32 copy of the values (mixed form)       */
     int32_t autotune;      /* 1: time launch shapes at create and keep the fastest       */
+                           /* (cg_create: reused for later matrices of the same size    */
+                           /* and row profile; cg_batch_create: the tile width)         */
     int32_t nnz_per_lane;  /* 4, 8 or 16: a product tile holds 64x that; 0 = default  */
                            /* (16, or 8 for the single-reduction form)                 */
     int32_t blocks_per_cu; /* 0 = default; workgroups per compute unit of the grid      */
@@ -103,6 +105,9 @@ typedef struct {
     int32_t tiles;         /* product tiles (runs of whole rows) of the matrix    */
     int32_t chunk;         /* iterations per hipGraph chunk                       */
     int32_t form;          /* CG_FORM_STANDARD or CG_FORM_SINGLE_REDUCTION        */
+    int32_t tune_cached;   /* 1: the autotuner reused the shape it chose earlier in
+                              this process for a matrix of the same size and
+                              row-length profile (no timing at this create)     */
     double spmv_us;        /* autotuner's best spmv time, 0 if not tuned          */
     double iter_us;        /* autotuner's best solver time per iteration, or 0    */
 } cg_config;

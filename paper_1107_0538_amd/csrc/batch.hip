@@ -203,6 +203,50 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
     if (opts) o = *opts; else cg_opts_default(&o);
     if (o.precond == CG_PRECOND_DEFAULT) o.precond = CG_PRECOND_JACOBI;
     if (o.precond != CG_PRECOND_JACOBI && o.precond != CG_PRECOND_NONE) return CG_EINVAL;
+    if (o.autotune) {
+        // Build the batch at each tile width, time 20 iterations of every
+        // system (tol 0, b = 1) and keep the fastest.
+        cg_batch* best = nullptr;
+        double best_s = 1e300;
+        int last_rc = CG_EINVAL;
+        for (int npl : {4, 8, 16}) {
+            cg_opts o2 = o;
+            o2.autotune = 0;
+            o2.nnz_per_lane = npl;
+            cg_batch* cand = nullptr;
+            last_rc = cg_batch_create(nsys, systems, &o2, hip_stream, &cand);
+            if (last_rc != 0) {
+                if (last_rc == CG_EINVAL || last_rc == CG_EDIAG) return last_rc;  // input errors
+                continue;
+            }
+            double t = 1e300;
+            double *bv = nullptr, *xv = nullptr;
+            std::vector<cg_info> info(nsys);
+            try {
+                const size_t bytes = sizeof(double) * (size_t)cand->n_total;
+                JPCG_HIP(hipMalloc(&bv, bytes));
+                JPCG_HIP(hipMalloc(&xv, bytes));
+                std::vector<double> ones(cand->n_total, 1.0);
+                JPCG_HIP(hipMemcpyAsync(bv, ones.data(), bytes, hipMemcpyHostToDevice, cand->stream));
+                JPCG_HIP(hipMemsetAsync(xv, 0, bytes, cand->stream));
+                if (cg_batch_solve(cand, bv, xv, 0.0, 20, info.data()) >= 0) t = info[0].seconds;
+            } catch (const HipError&) {
+                t = 1e300;
+            }
+            if (bv) (void)hipFree(bv);
+            if (xv) (void)hipFree(xv);
+            if (t < best_s) {
+                cg_batch_destroy(best);
+                best = cand;
+                best_s = t;
+            } else {
+                cg_batch_destroy(cand);
+            }
+        }
+        if (!best) return last_rc != 0 ? last_rc : CG_EHIP;
+        *out = best;
+        return 0;
+    }
     cg_batch* b = nullptr;
     try {
         b = new cg_batch();

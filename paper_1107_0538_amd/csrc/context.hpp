@@ -58,6 +58,7 @@ struct cg_ctx {
     int chunk = 16;
     double tuned_spmv_us = 0.0;
     double tuned_iter_us = 0.0;
+    bool tune_cached = false;  // the tuned shape came from an earlier context
 
     std::string err;
 };

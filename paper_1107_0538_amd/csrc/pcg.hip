@@ -23,6 +23,9 @@
 // residual check (and the residual replacement, if the check fails) between
 // chunks, exactly where the FP64 oracle does.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -631,8 +634,50 @@ static int default_grid(cg_ctx* c, int npl, int bs, int blocks_per_cu)
 
 // Time short solves over tile shapes (nonzeros per lane, block size,
 // workgroups per CU) and keep the fastest; record its standalone product time.
+// Tuned shapes, kept for the life of the process and reused by later
+// contexts whose matrix has the same size and row-length profile.
+struct TuneKey {
+    int device, n, maxrow, form, chunk;
+    int64_t nnz;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(device, n, maxrow, form, chunk, nnz) < std::tie(o.device, o.n, o.maxrow, o.form, o.chunk, o.nnz);
+    }
+};
+struct TuneResult {
+    int npl, bs, G;
+    double iter_us, spmv_us;
+};
+static std::mutex g_tune_mutex;
+static std::map<TuneKey, TuneResult> g_tune_cache;
+
+static TuneKey tune_key(const cg_ctx* c)
+{
+    int maxrow = 0;
+    for (int i = 0; i < c->n; ++i) maxrow = std::max(maxrow, c->h_rowptr[i + 1] - c->h_rowptr[i]);
+    return TuneKey{c->device, c->n, maxrow, c->form, c->chunk, c->nnz};
+}
+
 static void autotune(cg_ctx* c)
 {
+    const TuneKey key = tune_key(c);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            const TuneResult& r = it->second;
+            cg_graphs* g = make_graphs(c, c->form, false, r.npl, r.bs, r.G, c->chunk);
+            destroy_graphs(c->graphs);
+            c->graphs = g;
+            c->npl = r.npl;
+            c->bs = r.bs;
+            c->grid = r.G;
+            c->tuned_iter_us = r.iter_us;
+            c->tuned_spmv_us = r.spmv_us;
+            c->tune_cached = true;
+            return;
+        }
+    }
     double *xb = nullptr, *yb = nullptr;
     JPCG_HIP(hipMalloc(&xb, sizeof(double) * c->n));
     JPCG_HIP(hipMalloc(&yb, sizeof(double) * c->n));
@@ -695,6 +740,8 @@ static void autotune(cg_ctx* c)
     JPCG_HIP(hipEventDestroy(e1));
     JPCG_HIP(hipFree(xb));
     JPCG_HIP(hipFree(yb));
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune_cache[key] = TuneResult{c->npl, c->bs, c->grid, c->tuned_iter_us, c->tuned_spmv_us};
 }
 
 static void free_ctx(cg_ctx* c)
@@ -990,6 +1037,7 @@ int cg_get_config(cg_ctx* c, cg_config* cfg)
     cfg->tiles = c->graphs ? c->graphs->T : 0;
     cfg->chunk = c->chunk;
     cfg->form = c->form;
+    cfg->tune_cached = c->tune_cached ? 1 : 0;
     cfg->spmv_us = c->tuned_spmv_us;
     cfg->iter_us = c->tuned_iter_us;
     return 0;

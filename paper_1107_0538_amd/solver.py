@@ -198,7 +198,7 @@ class Solver:
 class Batch:
     """A cg_batch: many independent SPD CSR systems solved in one launch."""
 
-    def __init__(self, systems, precond="jacobi", nnz_per_lane=0, blocks_per_cu=0, stream=None):
+    def __init__(self, systems, precond="jacobi", nnz_per_lane=0, blocks_per_cu=0, autotune=False, stream=None):
         torch = _torch()
         self._lib = capi.load()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -211,7 +211,7 @@ class Batch:
                 raise ValueError("batched systems must be host (numpy) CSR matrices")
             arr[i] = csr
             self._keep.append(keep)
-        opts = make_opts(precond, nnz_per_lane=nnz_per_lane, blocks_per_cu=blocks_per_cu)
+        opts = make_opts(precond, autotune=autotune, nnz_per_lane=nnz_per_lane, blocks_per_cu=blocks_per_cu)
         h = ctypes.c_void_p()
         rc = self._lib.cg_batch_create(self.nsys, arr, ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
                                        ctypes.byref(h))

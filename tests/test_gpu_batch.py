@@ -119,3 +119,15 @@ def test_batch_systems_with_replacement(cuda):
     x = x.cpu().numpy()
     for s in range(7):
         check_system(mats[s], bs[s], x[bt.offsets[s]:bt.offsets[s + 1]], infos[s])
+
+
+def test_batch_autotune(cuda):
+    # The tile width is chosen by timing; the result must still match the oracle.
+    from paper_1107_0538_amd import Batch
+
+    sys = small_batch(8, seed=5)
+    bt = Batch([a for a, _ in sys], autotune=True)
+    x, infos = bt.solve(_t(np.concatenate([b for _, b in sys]), cuda))
+    x = x.cpu().numpy()
+    for s, (a, b) in enumerate(sys):
+        check_system(a, b, x[bt.offsets[s]:bt.offsets[s + 1]], infos[s])

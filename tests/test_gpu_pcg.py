@@ -256,6 +256,23 @@ def test_autotune_picks_valid_shape(cuda, form):
     assert abs(info["iters"] - io["iters"]) <= 2
 
 
+def test_autotune_cache(cuda):
+    # A second context on a matrix of the same size and row profile reuses the
+    # tuned shape without timing again.
+    from paper_1107_0538_amd import Solver
+
+    a, b = prob(16)
+    c1 = Solver(a, autotune=True).config()
+    a2, b2 = W.problem(16, 9)  # same pattern, other coefficients
+    s2 = Solver(a2, autotune=True)
+    c2 = s2.config()
+    assert c2["tune_cached"] == 1
+    assert (c1["nnz_per_lane"], c1["block_size"], c1["grid"]) == (c2["nnz_per_lane"], c2["block_size"], c2["grid"])
+    x, info = s2.solve(_t(b2, cuda))
+    xo, io = oracle.pcg(a2, b2)
+    assert info["status"] == 0 and abs(info["iters"] - io["iters"]) <= 2
+
+
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("maxit", [1, 2, 3, 16, 17, 18, 33])
 def test_iteration_limit_across_chunks(cuda, maxit, form):
