@@ -188,6 +188,23 @@ int cg_solve_multi(cg_ctx *ctx, const double *B, double *X, int32_t s, double to
                    cg_info *info);
 
 /*
+ * Multi-RHS mixed-precision solve: cg_solve_mixed's scheme applied to the
+ * columns of B together.  Repeat: R = B - A X in FP64 and the per-column FP64
+ * test; for the columns not yet converged, solve A D = R / ||r_j|| with the
+ * FP32 multi-RHS Jacobi-PCG on the FP32 copy of A (row-sum-preserving
+ * product, FP64 dot products) until each column's recurrence residual is
+ * <= tol_inner; X += ||r_j|| D.  At most maxit_outer rounds (<= 0: 50); each
+ * inner solve at most maxit_inner iterations (<= 0: n); tol_inner = 0 means
+ * 1e-5.  Requires fp32_copy = 1 (else CG_EINVAL).  B, X, s as in
+ * cg_solve_multi; info[j].iters counts column j's FP32 iterations,
+ * info[j].outer the rounds, info[j].relres_true its FP64 relative residual.
+ * Returns CG_CONVERGED if every column converged, else the largest column
+ * status (CG_MAXIT, CG_BREAKDOWN for non-finite input), or an API error.
+ */
+int cg_solve_multi_mixed(cg_ctx *ctx, const double *B, double *X, int32_t s, double tol, int32_t maxit_outer,
+                         double tol_inner, int32_t maxit_inner, cg_info *info);
+
+/*
  * Batched solves: nsys independent SPD systems solved together in one
  * persistent kernel launch (captured in a hipGraph).  systems[s] must be in
  * host memory (mem = CG_MEM_HOST) and is validated like cg_create's input;

@@ -42,6 +42,7 @@ struct cg_ctx {
     void* mixed_dev = nullptr;
     void* mixed_host = nullptr;
     struct cg_multi* multi = nullptr;        // multi-RHS solver for one block width
+    struct cg_multi* multi32 = nullptr;      // FP32 multi-RHS inner solver (mixed form)
     double* hist = nullptr;
     int hist_cap = 0;
     int hist_len = 0;

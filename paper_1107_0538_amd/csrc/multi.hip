@@ -24,6 +24,7 @@
 // order; whether any column is still active is read from the 64 statuses by
 // every kernel that needs it.
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -79,6 +80,8 @@ struct MrArgs {
     MrState* st;
     int maxit;
     double tol;
+    const T* rowsum;  // FP32 solves: row sums of A (FP64 sums) for the row-sum-preserving product
+    int confirm;      // 1: a passed recurrence test is confirmed on b - A x; 0: it ends the column
 };
 
 __device__ __forceinline__ int mr_logical(int G) { return xcd_logical_block((int)blockIdx.x, G); }
@@ -144,6 +147,33 @@ __device__ __forceinline__ bool mr_any_active(const MrState* st)
 {
     const int lane = threadIdx.x & (kWave - 1);
     return __ballot(st->status[lane] == COL_ACTIVE) != 0ull;
+}
+
+// Row-sum-preserving form of the same row product for the FP32 inner solve:
+// y_i = sum_k a_ik (x_j - x_i) + s_i x_i with s_i the row sum (summed in
+// FP64), so the near-constant modes of A are not lost to FP32 cancellation.
+template <typename T, typename Gather>
+__device__ __forceinline__ T mr_row_diff(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                         const T* __restrict__ val, const T* __restrict__ rowsum, int i, T xi,
+                                         Gather gather)
+{
+    constexpr int B = 16;
+    static_assert(B <= kCsrPad, "batch reads must stay within the padded arrays");
+    i = __builtin_amdgcn_readfirstlane(i);
+    const int k0 = __builtin_amdgcn_readfirstlane(rowptr[i]), k1 = __builtin_amdgcn_readfirstlane(rowptr[i + 1]);
+    T acc = T(0);
+    for (int k = k0; k < k1; k += B) {
+        T v[B], g[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            v[u] = val[k + u];
+            g[u] = gather(col[k + u]);
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (k + u < k1) acc = fma_t(v[u], g[u] - xi, acc);
+    }
+    return fma_t(rowsum[i], xi, acc);
 }
 
 // Residual R = B - A X with Z = M^-1 R and partials (r'r, r'z, b'b) per column.
@@ -226,8 +256,11 @@ __global__ __launch_bounds__(BS) void k_mr_direction(MrArgs<T> a, int P)
     const T* __restrict__ pnew = a.P[P];
     double v[1] = {0.0};
     for (int i = rs + w; i < re; i += BS / kWave) {
-        const T qi = mr_row<T>(a.rowptr, a.col, a.val, i, [&](int j) { return pnew[(size_t)j * s + cl]; });
         const size_t o = (size_t)i * s + cl;
+        auto gather = [&](int j) { return pnew[(size_t)j * s + cl]; };
+        T qi;
+        if constexpr (sizeof(T) == 4) qi = mr_row_diff<T>(a.rowptr, a.col, a.val, a.rowsum, i, pnew[o], gather);
+        else qi = mr_row<T>(a.rowptr, a.col, a.val, i, gather);
         if (used) {
             a.Q[o] = qi;
             if (active) v[0] += (double)pnew[o] * (double)qi;
@@ -343,7 +376,8 @@ __global__ __launch_bounds__(256) void k_mr_scalars(MrArgs<T> a, int phase)
         st->first[j] = 0;
         st->rr[j] = g[1];
         if (sqrt(g[1]) <= st->thr[j]) {
-            status = COL_PENDING;
+            status = a.confirm ? COL_PENDING : COL_CONVERGED;
+            if (!a.confirm) st->rr_true[j] = g[1];
         } else if (!(g[0] > 0.0) || !isfinite(g[0])) {
             status = COL_BREAKDOWN;
         } else if (st->iters[j] >= a.maxit) {
@@ -371,6 +405,35 @@ __global__ __launch_bounds__(256) void k_mr_scalars(MrArgs<T> a, int phase)
         if (status != COL_ZERO) st->rr_true[j] = g[0];
     }
     st->status[j] = status;
+}
+
+// Mixed form, outer step: B32 = R64 / ||r_j|| for the columns still active
+// in the FP64 state (0 for the others), X32 = 0.
+__global__ void k_mr_scale(int n, int s, const double* __restrict__ r64, const MrState* st64,
+                           float* __restrict__ b32, float* __restrict__ x32)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    if (lane >= s) return;
+    const bool active = st64->status[lane] == COL_ACTIVE;
+    const double nr = sqrt(st64->rr[lane]);
+    const double inv = active && nr > 0.0 ? 1.0 / nr : 0.0;
+    for (int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < n; i += gridDim.x * (blockDim.x / kWave)) {
+        const size_t o = (size_t)i * s + lane;
+        b32[o] = (float)(r64[o] * inv);
+        x32[o] = 0.0f;
+    }
+}
+
+// Mixed form: X64 += ||r_j|| X32 for the columns that were active.
+__global__ void k_mr_fold(int n, int s, double* __restrict__ x64, const float* __restrict__ x32, const MrState* st64)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    if (lane >= s || st64->status[lane] != COL_ACTIVE) return;
+    const double nr = sqrt(st64->rr[lane]);
+    for (int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < n; i += gridDim.x * (blockDim.x / kWave)) {
+        const size_t o = (size_t)i * s + lane;
+        x64[o] = fma(nr, (double)x32[o], x64[o]);
+    }
 }
 
 // x_j = 0 for columns with b_j = 0.
@@ -404,16 +467,19 @@ constexpr int kMrBS = 512;
 
 }  // namespace jpcg
 
-// Multi-RHS solver state hanging off a context, for one block width s.
+// Multi-RHS solver state hanging off a context, for one block width s and
+// one precision (FP64, or the FP32 inner solver of the mixed form).
 struct cg_multi {
     int s = 0, G = 0, chunk = 0;
-    double* work = nullptr;  // R, Z, P0, P1, Q, and the solver's own B, X: 7 N s doubles
+    bool fp32 = false;
+    void* work = nullptr;  // R, Z, P0, P1, Q, and the solver's own B, X: 7 N s values
     double* part = nullptr;
     jpcg::MrState* st = nullptr;
     jpcg::MrState* hst = nullptr;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipEvent_t ev = nullptr;
     jpcg::MrArgs<double> args{};
+    jpcg::MrArgs<float> args32{};
 };
 
 namespace jpcg {
@@ -436,41 +502,59 @@ static void mr_launch(const void* fn, int grid, int bs, hipStream_t st, void** a
     JPCG_HIP(hipLaunchKernel(fn, dim3(grid), dim3(bs), args, 0, st));
 }
 
+template <typename T>
+static MrArgs<T>& margs(cg_multi* m);
+template <>
+MrArgs<double>& margs<double>(cg_multi* m) { return m->args; }
+template <>
+MrArgs<float>& margs<float>(cg_multi* m) { return m->args32; }
+
+template <typename T>
 static cg_multi* make_multi(cg_ctx* c, int s)
 {
     cg_multi* m = new cg_multi();
     try {
         m->s = s;
+        m->fp32 = sizeof(T) == 4;
         m->chunk = 8;
         m->G = std::max(8, std::min(c->cus * 2, (c->n + 63) / 64) / 8 * 8);
         const size_t ns = (size_t)c->n * s;
-        JPCG_HIP(hipMalloc(&m->work, sizeof(double) * ns * 7));
+        JPCG_HIP(hipMalloc(&m->work, sizeof(T) * ns * 7));
         JPCG_HIP(hipMalloc(&m->part, sizeof(double) * (size_t)m->G * 3 * kWave));
         JPCG_HIP(hipMalloc(&m->st, sizeof(MrState)));
         JPCG_HIP(hipHostMalloc(&m->hst, sizeof(MrState), hipHostMallocDefault));
         JPCG_HIP(hipEventCreateWithFlags(&m->ev, hipEventDisableTiming));
-        JPCG_HIP(hipMemsetAsync(m->work, 0, sizeof(double) * ns * 7, c->stream));
+        JPCG_HIP(hipMemsetAsync(m->work, 0, sizeof(T) * ns * 7, c->stream));
         JPCG_HIP(hipMemsetAsync(m->st, 0, sizeof(MrState), c->stream));
-        MrArgs<double>& a = m->args;
+        MrArgs<T>& a = margs<T>(m);
+        T* w = (T*)m->work;
         a.n = c->n;
         a.s = s;
         a.rowptr = c->rowptr;
         a.col = c->col;
-        a.val = c->val;
-        a.dinv = c->dinv;
-        a.R = m->work;
-        a.Z = m->work + ns;
-        a.P[0] = m->work + 2 * ns;
-        a.P[1] = m->work + 3 * ns;
-        a.Q = m->work + 4 * ns;
-        a.B = m->work + 5 * ns;
-        a.X = m->work + 6 * ns;
+        if constexpr (sizeof(T) == 4) {
+            a.val = c->val32;
+            a.dinv = c->dinv32;
+            a.rowsum = c->rowsum32;
+        } else {
+            a.val = c->val;
+            a.dinv = c->dinv;
+            a.rowsum = nullptr;
+        }
+        a.R = w;
+        a.Z = w + ns;
+        a.P[0] = w + 2 * ns;
+        a.P[1] = w + 3 * ns;
+        a.Q = w + 4 * ns;
+        a.B = w + 5 * ns;
+        a.X = w + 6 * ns;
         a.G = m->G;
         a.rows_per_block = (c->n + m->G - 1) / m->G;
         a.part = m->part;
         a.st = m->st;
         a.maxit = c->n;
         a.tol = 1e-10;
+        a.confirm = 1;
         JPCG_HIP(hipStreamSynchronize(c->stream));
         return m;
     } catch (...) {
@@ -479,7 +563,8 @@ static cg_multi* make_multi(cg_ctx* c, int s)
     }
 }
 
-// (Re)capture the chunk graphs; tol and maxit are kernel arguments.
+// (Re)capture the chunk graphs; tol, maxit and confirm are kernel arguments.
+template <typename T>
 static void capture_multi(cg_multi* m)
 {
     for (auto& e : m->exec)
@@ -487,6 +572,7 @@ static void capture_multi(cg_multi* m)
             (void)hipGraphExecDestroy(e);
             e = nullptr;
         }
+    MrArgs<T>& args = margs<T>(m);
     hipStream_t cap;
     JPCG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     for (int par = 0; par < 2; ++par) {
@@ -494,14 +580,14 @@ static void capture_multi(cg_multi* m)
         JPCG_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         for (int it = 0; it < m->chunk; ++it) {
             int P = (par + it) & 1, ph_sig = MR_SIGMA, ph_it = MR_ITER;
-            void* a0[] = {&m->args, &P};
-            mr_launch((const void*)k_mr_pnew<kMrBS, double>, m->G, kMrBS, cap, a0);
-            mr_launch((const void*)k_mr_direction<kMrBS, double>, m->G, kMrBS, cap, a0);
-            void* a1[] = {&m->args, &ph_sig};
-            mr_launch((const void*)k_mr_scalars<double>, kCols, 256, cap, a1);
-            mr_launch((const void*)k_mr_update<kMrBS, double>, m->G, kMrBS, cap, a0);
-            void* a2[] = {&m->args, &ph_it};
-            mr_launch((const void*)k_mr_scalars<double>, kCols, 256, cap, a2);
+            void* a0[] = {&args, &P};
+            mr_launch((const void*)k_mr_pnew<kMrBS, T>, m->G, kMrBS, cap, a0);
+            mr_launch((const void*)k_mr_direction<kMrBS, T>, m->G, kMrBS, cap, a0);
+            void* a1[] = {&args, &ph_sig};
+            mr_launch((const void*)k_mr_scalars<T>, kCols, 256, cap, a1);
+            mr_launch((const void*)k_mr_update<kMrBS, T>, m->G, kMrBS, cap, a0);
+            void* a2[] = {&args, &ph_it};
+            mr_launch((const void*)k_mr_scalars<T>, kCols, 256, cap, a2);
         }
         JPCG_HIP(hipStreamEndCapture(cap, &graph));
         hipError_t e = hipGraphInstantiate(&m->exec[par], graph, nullptr, nullptr, 0);
@@ -515,6 +601,8 @@ void free_multi(cg_ctx* c)
 {
     destroy_multi(c->multi);
     c->multi = nullptr;
+    destroy_multi(c->multi32);
+    c->multi32 = nullptr;
 }
 
 static MrState mr_read(cg_ctx* c, cg_multi* m)
@@ -522,6 +610,89 @@ static MrState mr_read(cg_ctx* c, cg_multi* m)
     JPCG_HIP(hipMemcpyAsync(m->hst, m->st, sizeof(MrState), hipMemcpyDeviceToHost, c->stream));
     JPCG_HIP(hipStreamSynchronize(c->stream));
     return *m->hst;
+}
+
+// The context's multi-RHS solver of precision T for block width s, with its
+// graphs captured for (tol, maxit, confirm).
+template <typename T>
+static cg_multi* multi_for(cg_ctx* c, int s, double tol, int maxit, int confirm)
+{
+    cg_multi*& slot = sizeof(T) == 4 ? c->multi32 : c->multi;
+    if (!slot || slot->s != s) {
+        destroy_multi(slot);
+        slot = nullptr;
+        slot = make_multi<T>(c, s);
+    }
+    MrArgs<T>& a = margs<T>(slot);
+    if (!slot->exec[0] || a.tol != tol || a.maxit != maxit || a.confirm != confirm) {
+        a.tol = tol;
+        a.maxit = maxit;
+        a.confirm = confirm;
+        capture_multi<T>(slot);
+    }
+    return slot;
+}
+
+// One multi-RHS solve on the solver's own B and X: setup, chunks of
+// iterations, true-residual checks of waiting columns (confirm = 1), and the
+// final report.  Returns the final state.
+template <typename T>
+static MrState run_multi(cg_ctx* c, cg_multi* m)
+{
+    MrArgs<T>& args = margs<T>(m);
+    hipStream_t st = c->stream;
+    const int s = m->s;
+    int mode = 0, ph = MR_SETUP;
+    void* ra[] = {&args, &mode};
+    mr_launch((const void*)k_mr_residual<kMrBS, T>, m->G, kMrBS, st, ra);
+    void* sa[] = {&args, &ph};
+    mr_launch((const void*)k_mr_scalars<T>, kCols, 256, st, sa);
+    void* za[] = {&args};
+    mr_launch((const void*)k_mr_zero_cols<T>, 256, 256, st, za);
+    int next = 1;
+    const long long guard = 4LL * args.maxit + 64;
+    long long launched = 0;
+    while (true) {
+        MrState h = mr_read(c, m);
+        // Iterations after the last column stopped returned early, so the
+        // next iteration's parity comes from the device's count, not from
+        // the number of iterations launched.
+        next = h.kk + 1;
+        bool active = false, pending = false;
+        for (int j = 0; j < s; ++j) {
+            active = active || h.status[j] == COL_ACTIVE;
+            pending = pending || h.status[j] == COL_PENDING;
+        }
+        if (!active) {
+            if (!pending) break;
+            mode = 1;
+            ph = MR_CHECK;
+            mr_launch((const void*)k_mr_residual<kMrBS, T>, m->G, kMrBS, st, ra);
+            mr_launch((const void*)k_mr_scalars<T>, kCols, 256, st, sa);
+            continue;
+        }
+        if (launched > guard) throw HipError{hipErrorUnknown, "multi-RHS solver did not stop"};
+        // Two chunks per poll keep the device busy while the host reads.
+        JPCG_HIP(hipGraphLaunch(m->exec[next & 1], st));
+        next += m->chunk;
+        JPCG_HIP(hipGraphLaunch(m->exec[next & 1], st));
+        next += m->chunk;
+        launched += 2 * m->chunk;
+    }
+    if (args.confirm) {
+        mode = 2;
+        ph = MR_REPORT;
+        mr_launch((const void*)k_mr_residual<kMrBS, T>, m->G, kMrBS, st, ra);
+        mr_launch((const void*)k_mr_scalars<T>, kCols, 256, st, sa);
+    }
+    return mr_read(c, m);
+}
+
+static int col_code(int status)
+{
+    if (status == COL_MAXIT) return CG_MAXIT;
+    if (status == COL_BREAKDOWN) return CG_BREAKDOWN;
+    return CG_CONVERGED;
 }
 
 }  // namespace jpcg
@@ -553,73 +724,21 @@ int cg_solve_multi(cg_ctx* c, const double* B, double* X, int32_t s, double tol,
         return set_error(c, CG_EINVAL, "cg_solve_multi: bad arguments");
     if (maxit <= 0) maxit = c->n;
     try {
-        if (!c->multi || c->multi->s != s) {
-            destroy_multi(c->multi);
-            c->multi = nullptr;
-            c->multi = make_multi(c, s);
-        }
-        cg_multi* m = c->multi;
-        if (!m->exec[0] || m->args.tol != tol || m->args.maxit != maxit) {
-            m->args.tol = tol;
-            m->args.maxit = maxit;
-            capture_multi(m);
-        }
+        cg_multi* m = multi_for<double>(c, s, tol, maxit, 1);
         hipStream_t st = c->stream;
         const size_t nb = sizeof(double) * (size_t)c->n * s;
         JPCG_HIP(hipEventRecord(c->ev0, st));
         JPCG_HIP(hipMemcpyAsync((void*)m->args.B, B, nb, hipMemcpyDeviceToDevice, st));
         JPCG_HIP(hipMemcpyAsync(m->args.X, X, nb, hipMemcpyDeviceToDevice, st));
-        int mode = 0, ph = MR_SETUP;
-        void* ra[] = {&m->args, &mode};
-        mr_launch((const void*)k_mr_residual<kMrBS, double>, m->G, kMrBS, st, ra);
-        void* sa[] = {&m->args, &ph};
-        mr_launch((const void*)k_mr_scalars<double>, kCols, 256, st, sa);
-        void* za[] = {&m->args};
-        mr_launch((const void*)k_mr_zero_cols<double>, 256, 256, st, za);
-        int next = 1;
-        const long long guard = 4LL * maxit + 64;
-        long long launched = 0;
-        while (true) {
-            MrState h = mr_read(c, m);
-            // Iterations after the last column stopped returned early, so the
-            // next iteration's parity comes from the device's count, not from
-            // the number of iterations launched.
-            next = h.kk + 1;
-            bool active = false, pending = false;
-            for (int j = 0; j < s; ++j) {
-                active = active || h.status[j] == COL_ACTIVE;
-                pending = pending || h.status[j] == COL_PENDING;
-            }
-            if (!active) {
-                if (!pending) break;
-                mode = 1;
-                ph = MR_CHECK;
-                mr_launch((const void*)k_mr_residual<kMrBS, double>, m->G, kMrBS, st, ra);
-                mr_launch((const void*)k_mr_scalars<double>, kCols, 256, st, sa);
-                continue;
-            }
-            if (launched > guard) throw HipError{hipErrorUnknown, "multi-RHS solver did not stop"};
-            // Two chunks per poll keep the device busy while the host reads.
-            JPCG_HIP(hipGraphLaunch(m->exec[next & 1], st));
-            next += m->chunk;
-            JPCG_HIP(hipGraphLaunch(m->exec[next & 1], st));
-            next += m->chunk;
-            launched += 2 * m->chunk;
-        }
-        mode = 2;
-        ph = MR_REPORT;
-        mr_launch((const void*)k_mr_residual<kMrBS, double>, m->G, kMrBS, st, ra);
-        mr_launch((const void*)k_mr_scalars<double>, kCols, 256, st, sa);
+        const MrState h = run_multi<double>(c, m);
         JPCG_HIP(hipMemcpyAsync(X, m->args.X, nb, hipMemcpyDeviceToDevice, st));
         JPCG_HIP(hipEventRecord(c->ev1, st));
-        const MrState h = mr_read(c, m);
+        JPCG_HIP(hipEventSynchronize(c->ev1));
         float ms = 0.f;
         JPCG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
         int worst = CG_CONVERGED;
         for (int j = 0; j < s; ++j) {
-            int code = CG_CONVERGED;
-            if (h.status[j] == COL_MAXIT) code = CG_MAXIT;
-            else if (h.status[j] == COL_BREAKDOWN) code = CG_BREAKDOWN;
+            const int code = col_code(h.status[j]);
             worst = std::max(worst, code);
             if (info) {
                 cg_info& o = info[j];
@@ -635,6 +754,113 @@ int cg_solve_multi(cg_ctx* c, const double* B, double* X, int32_t s, double tol,
         return worst;
     } catch (const HipError& e) {
         return set_error(c, CG_EHIP, std::string("cg_solve_multi: ") + e.what + ": " + hipGetErrorString(e.code));
+    }
+}
+
+int cg_solve_multi_mixed(cg_ctx* c, const double* B, double* X, int32_t s, double tol, int32_t maxit_outer,
+                         double tol_inner, int32_t maxit_inner, cg_info* info)
+{
+    if (!c) return CG_EINVAL;
+    if (!c->val32) return set_error(c, CG_EINVAL, "cg_solve_multi_mixed: the context was created without fp32_copy");
+    if (!B || !X || B == X || s < 1 || s > kCols || !(tol >= 0.0) || !std::isfinite(tol) || !(tol_inner >= 0.0) ||
+        !std::isfinite(tol_inner))
+        return set_error(c, CG_EINVAL, "cg_solve_multi_mixed: bad arguments");
+    if (maxit_outer <= 0) maxit_outer = 50;
+    if (maxit_inner <= 0) maxit_inner = c->n;
+    if (tol_inner == 0.0) tol_inner = 1e-5;
+    try {
+        // The FP64 solver holds B, X and the outer residual (its setup phase
+        // is the FP64 test); the FP32 solver runs the inner solves.
+        cg_multi* m64 = multi_for<double>(c, s, tol, c->n, 1);
+        cg_multi* m32 = multi_for<float>(c, s, tol_inner, maxit_inner, 0);
+        hipStream_t st = c->stream;
+        const size_t nb = sizeof(double) * (size_t)c->n * s;
+        JPCG_HIP(hipEventRecord(c->ev0, st));
+        JPCG_HIP(hipMemcpyAsync((void*)m64->args.B, B, nb, hipMemcpyDeviceToDevice, st));
+        JPCG_HIP(hipMemcpyAsync(m64->args.X, X, nb, hipMemcpyDeviceToDevice, st));
+        int final_status[kCols];
+        int inner_iters[kCols] = {};
+        for (int j = 0; j < kCols; ++j) final_status[j] = -1;
+        int n = c->n;
+        const int eg = std::min(4096, (c->n + 3) / 4);
+        MrState h{};
+        int outer = 0;
+        for (;; ++outer) {
+            // r = b - A x in FP64 and the per-column tests.
+            int mode = 0, ph = MR_SETUP;
+            void* ra[] = {&m64->args, &mode};
+            mr_launch((const void*)k_mr_residual<kMrBS, double>, m64->G, kMrBS, st, ra);
+            void* sa[] = {&m64->args, &ph};
+            mr_launch((const void*)k_mr_scalars<double>, kCols, 256, st, sa);
+            if (outer == 0) {  // x_j = 0 for b_j = 0
+                void* za[] = {&m64->args};
+                mr_launch((const void*)k_mr_zero_cols<double>, 256, 256, st, za);
+            }
+            h = mr_read(c, m64);
+            bool any = false, changed = false;
+            for (int j = 0; j < s; ++j) {
+                if (final_status[j] >= 0) {  // decided earlier: keep it out of the inner solves
+                    if (h.status[j] == COL_ACTIVE) {
+                        h.status[j] = final_status[j] == CG_BREAKDOWN ? COL_BREAKDOWN : COL_MAXIT;
+                        changed = true;
+                    }
+                    continue;
+                }
+                if (!(h.rr[j] == h.rr[j]) || !(h.nb[j] == h.nb[j])) {  // NaN input
+                    final_status[j] = CG_BREAKDOWN;
+                    h.status[j] = COL_BREAKDOWN;
+                    changed = true;
+                } else if (h.status[j] != COL_ACTIVE) {
+                    final_status[j] = CG_CONVERGED;  // converged (or b_j = 0)
+                } else if (outer >= maxit_outer) {
+                    final_status[j] = CG_MAXIT;
+                    h.status[j] = COL_MAXIT;
+                    changed = true;
+                } else {
+                    any = true;
+                }
+            }
+            if (!any) break;
+            if (changed) {
+                int* dstatus = (int*)((char*)m64->st + offsetof(MrState, status));
+                JPCG_HIP(hipMemcpyAsync(dstatus, h.status, sizeof(int) * kCols, hipMemcpyHostToDevice, st));
+            }
+            // Scaled residual of the active columns into the FP32 solver.
+            const double* r64 = m64->args.R;
+            void* ka[] = {&n, &s, &r64, &m64->st, &m32->args32.B, &m32->args32.X};
+            mr_launch((const void*)k_mr_scale, eg, 256, st, ka);
+            const MrState hi = run_multi<float>(c, m32);
+            for (int j = 0; j < s; ++j)
+                if (h.status[j] == COL_ACTIVE) inner_iters[j] += hi.iters[j];
+            const float* x32 = m32->args32.X;
+            void* fa[] = {&n, &s, &m64->args.X, &x32, &m64->st};
+            mr_launch((const void*)k_mr_fold, eg, 256, st, fa);
+        }
+        JPCG_HIP(hipMemcpyAsync(X, m64->args.X, nb, hipMemcpyDeviceToDevice, st));
+        JPCG_HIP(hipEventRecord(c->ev1, st));
+        JPCG_HIP(hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        JPCG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        int worst = CG_CONVERGED;
+        for (int j = 0; j < s; ++j) {
+            const int code = final_status[j] < 0 ? CG_MAXIT : final_status[j];
+            worst = std::max(worst, code);
+            if (info) {
+                cg_info& o = info[j];
+                o.iters = inner_iters[j];
+                o.status = code;
+                o.replacements = 0;
+                o.outer = outer;
+                const double rel = h.nb[j] > 0 ? std::sqrt(h.rr[j]) / h.nb[j] : 0.0;
+                o.relres_recur = rel;
+                o.relres_true = rel;
+                o.seconds = ms * 1e-3;
+            }
+        }
+        return worst;
+    } catch (const HipError& e) {
+        return set_error(c, CG_EHIP,
+                         std::string("cg_solve_multi_mixed: ") + e.what + ": " + hipGetErrorString(e.code));
     }
 }
 

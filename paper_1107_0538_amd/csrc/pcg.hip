@@ -863,7 +863,8 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
             JPCG_HIP(hipMemcpyAsync(c->val, hval.data(), sizeof(double) * nnz, hipMemcpyHostToDevice, c->stream));
         }
         if (c->opts.fp32_copy) {
-            JPCG_HIP(hipMalloc(&c->val32, sizeof(float) * std::max<int64_t>(nnz, 1)));
+            JPCG_HIP(hipMalloc(&c->val32, sizeof(float) * (nnz + kCsrPad)));
+            JPCG_HIP(hipMemsetAsync(c->val32 + nnz, 0, sizeof(float) * kCsrPad, c->stream));
             JPCG_HIP(hipMalloc(&c->dinv32, sizeof(float) * n));
             JPCG_HIP(hipMalloc(&c->rowsum32, sizeof(float) * n));
             if (nnz) cast_f32_kernel<<<1024, 256, 0, c->stream>>>(nnz, c->val, c->val32);

@@ -182,6 +182,22 @@ class Solver:
         infos = self.cg_solve_multi(B, X, tol, maxit)
         return X, infos
 
+    def cg_solve_multi_mixed(self, B, X, tol=1e-10, maxit_outer=0, tol_inner=1e-5, maxit_inner=0) -> list:
+        self._as_block(B, "B")
+        self._as_block(X, "X")
+        s = B.shape[1]
+        infos = (capi.cg_info * s)()
+        rc = self._lib.cg_solve_multi_mixed(self.ctx, B.data_ptr(), X.data_ptr(), s, float(tol), int(maxit_outer),
+                                            float(tol_inner), int(maxit_inner), infos)
+        capi.check(rc, self.ctx)
+        return [infos[j].as_dict() for j in range(s)]
+
+    def solve_multi_mixed(self, B, X0=None, tol=1e-10, maxit_outer=0, tol_inner=1e-5, maxit_inner=0):
+        torch = _torch()
+        X = torch.zeros_like(B) if X0 is None else X0.clone()
+        infos = self.cg_solve_multi_mixed(B, X, tol, maxit_outer, tol_inner, maxit_inner)
+        return X, infos
+
     # -- introspection -------------------------------------------------------------
     def history(self) -> np.ndarray:
         cap = self.n + 1

@@ -151,3 +151,47 @@ def test_multi_rhs_block_width_changes(cuda):
             xo, io = oracle.pcg(a, B[:, j])
             assert infos[j]["status"] == 0 and abs(infos[j]["iters"] - io["iters"]) <= 2
             assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+@pytest.mark.parametrize("n,s", [(16, 64), (51, 8)])
+def test_multi_rhs_mixed_meets_fp64_tolerance(cuda, n, s):
+    # FP32 inner multi-RHS solves with FP64 refinement: every column meets the
+    # FP64 test, recomputed on the CPU.
+    from paper_1107_0538_amd import Solver
+
+    a = mat(n)
+    B = W.multi_rhs(a.n, s)
+    sv = Solver(a, fp32_copy=True)
+    X, infos = sv.solve_multi_mixed(_t(B, cuda))
+    X = X.cpu().numpy()
+    for j in range(s):
+        assert infos[j]["status"] == 0, (j, infos[j])
+        assert infos[j]["outer"] >= 1
+        assert oracle.relres(a, B[:, j], X[:, j]) <= TOL_RECOMPUTED
+    for j in (0, s - 1):
+        xo, io = oracle.pcg(a, B[:, j])
+        assert np.linalg.norm(X[:, j] - xo) / np.linalg.norm(xo) <= 1e-5
+
+
+def test_multi_rhs_mixed_columns_and_limits(cuda):
+    from paper_1107_0538_amd import Solver
+
+    a = mat(7)
+    rng = np.random.default_rng(4)
+    B = rng.uniform(-1, 1, (a.n, 5))
+    B[:, 1] = 0.0
+    B[2, 3] = np.nan
+    X0 = np.zeros_like(B)
+    X0[:, 1] = 1.0
+    sv = Solver(a, fp32_copy=True)
+    X, infos = sv.solve_multi_mixed(_t(B, cuda), X0=_t(X0, cuda))
+    X = X.cpu().numpy()
+    assert infos[1]["status"] == 0 and not X[:, 1].any()
+    assert infos[3]["status"] == 2
+    for j in (0, 2, 4):
+        assert infos[j]["status"] == 0 and oracle.relres(a, B[:, j], X[:, j]) <= TOL_RECOMPUTED
+    Bg = W.multi_rhs(a.n, 3, seed=8)
+    X, infos = sv.solve_multi_mixed(_t(Bg, cuda), maxit_outer=1, tol_inner=1e-2)
+    assert all(i["status"] == 1 and i["outer"] == 1 for i in infos)
+    with pytest.raises(ValueError):
+        Solver(a).solve_multi_mixed(_t(Bg, cuda))
