@@ -16,6 +16,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <queue>
 #include <vector>
 
 #include "context.hpp"
@@ -344,16 +345,22 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
             work[s] = (z_s + n_s) * std::cbrt(n_s);
             total += work[s];
         }
+        // The batch ends when its slowest team does, and a team's time goes
+        // as its work over its size: hand out the workgroups one at a time,
+        // each to the team with the largest work per member (which minimises
+        // the largest of those ratios), a team never larger than its tiles.
+        (void)total;
         b->team.assign(nsys, 1);
         int used = nsys;
-        for (int s = 0; s < nsys; ++s) {
-            const int want = std::max(1, (int)std::floor(work[s] / total * capacity));
-            const int ntiles = std::max(1, tile_off[s + 1] - tile_off[s]);
-            const int extra = std::min(want, ntiles) - 1;
-            if (used + extra <= capacity) {
-                b->team[s] += extra;
-                used += extra;
-            }
+        std::priority_queue<std::pair<double, int>> queue;
+        for (int s = 0; s < nsys; ++s) queue.push({work[s], s});
+        while (used < capacity && !queue.empty()) {
+            const int s = queue.top().second;
+            queue.pop();
+            if (b->team[s] >= std::max(1, tile_off[s + 1] - tile_off[s])) continue;  // no tile left to give
+            b->team[s] += 1;
+            used += 1;
+            queue.push({work[s] / b->team[s], s});
         }
         b->grid = used;
         // Per-workgroup tables.
