@@ -213,9 +213,9 @@ int cg_solve_multi_mixed(cg_ctx *ctx, const double *B, double *X, int32_t s, dou
  * with cg_solve's algorithm and stopping rules; its rows are cut into
  * product tiles and each workgroup of the team owns an equal run of them.
  * opts->precond applies to every system; opts->nnz_per_lane picks the tile
- * width (4, 8 or 16 nonzeros per lane, 0 = 8); opts->blocks_per_cu bounds the
- * workgroups per compute unit (0 = three quarters of the occupancy limit;
- * larger values are clamped to the limit, the most that can be co-resident).  Teams wait for each
+ * width (4, 8 or 16 nonzeros per lane, 0 = 16); opts->blocks_per_cu bounds the
+ * workgroups per compute unit (0 = the occupancy limit, the most that can be
+ * co-resident; larger values are clamped to it).  Teams wait for each
  * other at bounded barriers, so a device shared with other work while the
  * batch runs can end the solve with CG_ETIMEOUT.  At most one system per
  * co-resident workgroup slot (else CG_EINVAL).

@@ -253,7 +253,7 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         b = new cg_batch();
         b->stream = (hipStream_t)hip_stream;
         b->nsys = nsys;
-        b->npl = o.nnz_per_lane ? o.nnz_per_lane : 8;
+        b->npl = o.nnz_per_lane ? o.nnz_per_lane : 16;
         if (!batch_kernel(b->npl)) {
             free_batch(b);
             return CG_EINVAL;
@@ -319,8 +319,8 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
 
         // Teams: workgroups per system in proportion to nnz times rows^(1/3)
         // (CG iterations grow with the grid edge), at most one per tile,
-        // within the co-resident capacity (three quarters of the occupancy
-        // limit unless opts->blocks_per_cu asks for another count per CU).  The product streams
+        // within the co-resident capacity (the occupancy limit unless
+        // opts->blocks_per_cu asks for fewer per CU).  The product streams
         // the whole batch's matrices from HBM every iteration, so it wants as
         // many waves in flight as fit.
         int dev = 0, cus = 0, per_cu = 0, wall_khz = 0;
@@ -330,10 +330,7 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         JPCG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(b->npl), kBatchBS, 0));
         b->limit = (long long)std::max(wall_khz, 1000) * 1000LL * 8;  // 8 s of device wall clock
         const int bpc = o.blocks_per_cu > 0 ? std::min(o.blocks_per_cu, per_cu) : 0;
-        // A quarter of the slots stay free by default: filling every slot
-        // has left a team short of co-resident members (its barrier then
-        // times out) although the occupancy query allowed it.
-        const int capacity = std::max(nsys, std::max(1, bpc > 0 ? bpc * cus : per_cu * cus * 3 / 4));
+        const int capacity = std::max(nsys, std::max(1, (bpc > 0 ? bpc : per_cu) * cus));
         if (nsys > per_cu * cus) {  // one workgroup per system must still be co-resident
             free_batch(b);
             return CG_EINVAL;
