@@ -477,13 +477,14 @@ def main():
     if not args.no_cpu:
         import oracle
 
-        reps = 2
-        log(f"cpu baseline: {reps} oracle solves")
+        # A bounded sample: whole oracle solves until about 12 s of CPU work.
         ts = []
-        for _ in range(reps):
+        while len(ts) < 2 or (sum(ts) < 12.0 and len(ts) < 50):
             t = time.perf_counter()
             xo, io = oracle.pcg(a, b, tol=1e-10)
             ts.append(time.perf_counter() - t)
+        reps = len(ts)
+        log(f"cpu baseline: {reps} oracle solves, {sum(ts):.1f} s")
         out["cpu_baseline"] = {
             "value": statistics.mean(ts), "unit": "s", "cores": 1, "kind": "oracle",
             "sample": f"{reps} full FP64 Jacobi-PCG solves of the same {args.n}^3 system "
