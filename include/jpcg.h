@@ -153,7 +153,7 @@ int cg_solve(cg_ctx *ctx, const double *b, double *x, double tol, int32_t maxit,
  *     dot products) from d = 0 until its recurrence residual is <= tol_inner;
  *   x += ||r|| d in FP64,
  * at most maxit_outer times (<= 0: 50); each inner solve runs at most
- * maxit_inner iterations (<= 0: n); tol_inner = 0 means 1e-5.  Requires a
+ * maxit_inner iterations (<= 0: n); tol_inner = 0 means 1e-3.  Requires a
  * context created with fp32_copy = 1, else CG_EINVAL.  b, x as in cg_solve.
  * info->iters counts inner iterations, info->outer refinement steps, and
  * info->relres_true is the FP64 ||b - A x|| / ||b|| of the returned x.
@@ -195,7 +195,7 @@ int cg_solve_multi(cg_ctx *ctx, const double *B, double *X, int32_t s, double to
  * product, FP64 dot products) until each column's recurrence residual is
  * <= tol_inner; X += ||r_j|| D.  At most maxit_outer rounds (<= 0: 50); each
  * inner solve at most maxit_inner iterations (<= 0: n); tol_inner = 0 means
- * 1e-5.  Requires fp32_copy = 1 (else CG_EINVAL).  B, X, s as in
+ * 1e-3.  Requires fp32_copy = 1 (else CG_EINVAL).  B, X, s as in
  * cg_solve_multi; info[j].iters counts column j's FP32 iterations,
  * info[j].outer the rounds, info[j].relres_true its FP64 relative residual.
  * Returns CG_CONVERGED if every column converged, else the largest column

@@ -767,7 +767,7 @@ int cg_solve_multi_mixed(cg_ctx* c, const double* B, double* X, int32_t s, doubl
         return set_error(c, CG_EINVAL, "cg_solve_multi_mixed: bad arguments");
     if (maxit_outer <= 0) maxit_outer = 50;
     if (maxit_inner <= 0) maxit_inner = c->n;
-    if (tol_inner == 0.0) tol_inner = 1e-5;
+    if (tol_inner == 0.0) tol_inner = 1e-3;
     try {
         // The FP64 solver holds B, X and the outer residual (its setup phase
         // is the FP64 test); the FP32 solver runs the inner solves.

@@ -980,7 +980,7 @@ int cg_solve_mixed(cg_ctx* c, const double* b, double* x, double tol, int32_t ma
         return set_error(c, CG_EINVAL, "cg_solve_mixed: bad arguments");
     if (maxit_outer <= 0) maxit_outer = 50;
     if (maxit_inner <= 0) maxit_inner = c->n;
-    if (tol_inner == 0.0) tol_inner = 1e-5;
+    if (tol_inner == 0.0) tol_inner = 1e-3;
     try {
         JPCG_HIP(hipEventRecord(c->ev0, c->stream));
         const MixedResult r = run_mixed(c, b, x, tol, maxit_outer, tol_inner, maxit_inner);

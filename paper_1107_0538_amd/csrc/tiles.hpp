@@ -65,6 +65,27 @@ __device__ __forceinline__ T lds_row_sum(const T* prod, int a, int b)
     return s;
 }
 
+// The row-sum-preserving row sum: sum of prod[k] * (px[k] - xi) over [a, b)
+// in order, with eight of each LDS array read per batch.
+template <typename T>
+__device__ __forceinline__ T lds_row_sum_diff(const T* prod, const T* px, int a, int b, T xi)
+{
+    T s = T(0);
+    int k = a;
+    for (; k + 8 <= b; k += 8) {
+        T t[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            t[u] = prod[k + u];
+            y[u] = px[k + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += t[u] * (y[u] - xi);
+    }
+    for (; k < b; ++k) s += prod[k] * (px[k] - xi);
+    return s;
+}
+
 // Visit every row of the workgroup's tiles.
 //   gather(j)       raw operand(s) of column j (type GV), loaded per nonzero
 //   value(g)        the vector entry x_j from the raw operands (may use scalars
@@ -151,8 +172,7 @@ __device__ __forceinline__ void tile_rows_x(const int* __restrict__ rowptr, cons
                 const int a = (i == i0 ? ra : rowptr[i]) - k0, b = (i == i0 ? rb : rowptr[i + 1]) - k0;
                 if constexpr (DIFF) {
                     const T xi = self(pvi);
-                    T s = T(0);
-                    for (int k = a; k < b; ++k) s += prod[k] * (px[k] - xi);
+                    const T s = lds_row_sum_diff(prod, px, a, b, xi);
                     row(i, s + rowsum[i] * xi, pvi);
                 } else {
                     row(i, lds_row_sum(prod, a, b), pvi);

@@ -125,7 +125,7 @@ class Solver:
         info = self.cg_solve(b, x, tol, maxit)
         return x, info
 
-    def cg_solve_mixed(self, b, x, tol=1e-10, maxit_outer=0, tol_inner=1e-5, maxit_inner=0) -> dict:
+    def cg_solve_mixed(self, b, x, tol=1e-10, maxit_outer=0, tol_inner=0.0, maxit_inner=0) -> dict:
         """In-place mixed-precision solve (FP32 inner CG, FP64 refinement)."""
         _as_device_vec(b, self.n, "b")
         _as_device_vec(x, self.n, "x")
@@ -135,7 +135,7 @@ class Solver:
         capi.check(rc, self.ctx)
         return info.as_dict()
 
-    def solve_mixed(self, b, x0=None, tol=1e-10, maxit_outer=0, tol_inner=1e-5, maxit_inner=0):
+    def solve_mixed(self, b, x0=None, tol=1e-10, maxit_outer=0, tol_inner=0.0, maxit_inner=0):
         torch = _torch()
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         info = self.cg_solve_mixed(b, x, tol, maxit_outer, tol_inner, maxit_inner)
@@ -182,7 +182,7 @@ class Solver:
         infos = self.cg_solve_multi(B, X, tol, maxit)
         return X, infos
 
-    def cg_solve_multi_mixed(self, B, X, tol=1e-10, maxit_outer=0, tol_inner=1e-5, maxit_inner=0) -> list:
+    def cg_solve_multi_mixed(self, B, X, tol=1e-10, maxit_outer=0, tol_inner=0.0, maxit_inner=0) -> list:
         self._as_block(B, "B")
         self._as_block(X, "X")
         s = B.shape[1]
@@ -192,7 +192,7 @@ class Solver:
         capi.check(rc, self.ctx)
         return [infos[j].as_dict() for j in range(s)]
 
-    def solve_multi_mixed(self, B, X0=None, tol=1e-10, maxit_outer=0, tol_inner=1e-5, maxit_inner=0):
+    def solve_multi_mixed(self, B, X0=None, tol=1e-10, maxit_outer=0, tol_inner=0.0, maxit_inner=0):
         torch = _torch()
         X = torch.zeros_like(B) if X0 is None else X0.clone()
         infos = self.cg_solve_multi_mixed(B, X, tol, maxit_outer, tol_inner, maxit_inner)
