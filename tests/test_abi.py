@@ -3,6 +3,8 @@ function, and rejects bad arguments before touching the device."""
 import ctypes
 import subprocess
 
+import pytest
+
 from paper_1107_0538_amd import capi
 
 
@@ -41,3 +43,13 @@ def test_opts_default():
     o = capi.cg_opts()
     capi.load().cg_opts_default(ctypes.byref(o))
     assert o.precond == capi.CG_PRECOND_JACOBI and o.autotune == 0 and o.fp32_copy == 0
+
+
+def test_load_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    # No CPU fallback: a missing library is an error, not a silent substitute.
+    from paper_1107_0538_amd import capi
+
+    monkeypatch.setattr(capi, "_lib", None)
+    monkeypatch.setattr(capi, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError):
+        capi.load()

@@ -131,3 +131,20 @@ def test_batch_autotune(cuda):
     x = x.cpu().numpy()
     for s, (a, b) in enumerate(sys):
         check_system(a, b, x[bt.offsets[s]:bt.offsets[s + 1]], infos[s])
+
+
+def test_batch_single_and_tiny_systems(cuda):
+    # One system alone, and a batch mixing 1 x 1 systems with a 3-D one.
+    from paper_1107_0538_amd import Batch
+
+    a, b = W.problem(6, 2)
+    bt = Batch([a])
+    x, infos = bt.solve(_t(b, cuda))
+    check_system(a, b, x.cpu().numpy(), infos[0])
+    one = W.CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.0]))
+    bt = Batch([one, a, one])
+    x, infos = bt.solve(_t(np.concatenate([[4.0], b, [-6.0]]), cuda))
+    x = x.cpu().numpy()
+    assert infos[0]["status"] == infos[2]["status"] == 0
+    assert abs(x[0] - 2.0) <= 1e-15 and abs(x[-1] + 3.0) <= 1e-15
+    check_system(a, b, x[1:-1], infos[1])

@@ -351,3 +351,23 @@ def test_block_sizes(cuda, bs, form):
     x, info = s.solve(_t(b, cuda))
     assert abs(info["iters"] - io["iters"]) <= 2
     assert np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_tiny_systems(cuda, form):
+    # 1 x 1 and 2 x 2 systems: one or two iterations, exact against the oracle.
+    from paper_1107_0538_amd import Solver
+
+    one = W.CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([4.0]))
+    s = Solver(one, form=form)
+    x, info = s.solve(_t(np.array([2.0]), cuda))
+    assert info["status"] == 0 and info["iters"] == 1
+    assert abs(x.cpu().numpy()[0] - 0.5) <= 1e-15
+    y = s.spmv(_t(np.array([3.0]), cuda)).cpu().numpy()
+    assert y[0] == 12.0
+    two = W.CSR(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32), np.array([2.0, -1.0, -1.0, 3.0]))
+    b = np.array([1.0, 2.0])
+    x, info = Solver(two, form=form, precond="none").solve(_t(b, cuda))
+    xo, io = oracle.pcg(two, b, precond="none", form=form)
+    assert info["status"] == io["status"] == 0 and info["iters"] == io["iters"] <= 2
+    assert np.linalg.norm(x.cpu().numpy() - np.linalg.solve(two.to_dense(), b)) <= 1e-14
