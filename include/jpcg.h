@@ -83,7 +83,11 @@ typedef struct {
     int32_t block_size;    /* 0 = default; else 256, 512 or 1024 threads per workgroup  */
     int32_t chunk;         /* 0 = default; CG iterations per launched hipGraph chunk    */
     int32_t form;          /* CG_FORM_STANDARD (default) or CG_FORM_SINGLE_REDUCTION    */
-    int32_t reserved[7];   /* must be zero                                               */
+    int32_t col_bits;      /* 0 = default: the products read 16-bit column offsets from */
+                           /* each tile's first row where every one fits (10 bytes per  */
+                           /* FP64 nonzero instead of 12; same sums), else 32-bit       */
+                           /* columns; 32 = always 32-bit columns                       */
+    int32_t reserved[6];   /* must be zero                                               */
 } cg_opts;
 
 /* Result of a solve. */
@@ -108,6 +112,7 @@ typedef struct {
     int32_t tune_cached;   /* 1: the autotuner reused the shape it chose earlier in
                               this process for a matrix of the same size and
                               row-length profile (no timing at this create)     */
+    int32_t col_bits;      /* 16 or 32: column index width the products read      */
     double spmv_us;        /* autotuner's best spmv time, 0 if not tuned          */
     double iter_us;        /* autotuner's best solver time per iteration, or 0    */
 } cg_config;
@@ -215,7 +220,9 @@ int cg_solve_multi_mixed(cg_ctx *ctx, const double *B, double *X, int32_t s, dou
  * opts->precond applies to every system; opts->nnz_per_lane picks the tile
  * width (4, 8 or 16 nonzeros per lane, 0 = 16); opts->blocks_per_cu bounds the
  * workgroups per compute unit (0 = the occupancy limit, the most that can be
- * co-resident; larger values are clamped to it).  Teams wait for each
+ * co-resident; larger values are clamped to it); opts->col_bits as for
+ * cg_create (the 16-bit form is used only if it fits every system's tiles).
+ * Teams wait for each
  * other at bounded barriers, so a device shared with other work while the
  * batch runs can end the solve with CG_ETIMEOUT.  At most one system per
  * co-resident workgroup slot (else CG_EINVAL).

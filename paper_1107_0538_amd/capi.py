@@ -32,7 +32,7 @@ class cg_opts(ctypes.Structure):
     _fields_ = [("precond", ctypes.c_int32), ("fp32_copy", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("nnz_per_lane", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("history", ctypes.c_int32), ("block_size", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("form", ctypes.c_int32), ("col_bits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class cg_info(ctypes.Structure):
@@ -47,7 +47,7 @@ class cg_info(ctypes.Structure):
 class cg_config(ctypes.Structure):
     _fields_ = [("nnz_per_lane", ctypes.c_int32), ("block_size", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("tiles", ctypes.c_int32), ("chunk", ctypes.c_int32), ("form", ctypes.c_int32),
-                ("tune_cached", ctypes.c_int32), ("spmv_us", ctypes.c_double), ("iter_us", ctypes.c_double)]
+                ("tune_cached", ctypes.c_int32), ("col_bits", ctypes.c_int32), ("spmv_us", ctypes.c_double), ("iter_us", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -39,6 +39,7 @@ struct BatchArgs {
     const int* team_size;    // per system
     const int* part_off;     // per system: offset of its NSLOT * team_size partials
     const int4* tiles;       // every system's product tiles, global rows and nonzeros
+    const unsigned short* col16;  // narrow column indices of those tiles, or null
     const int* tile_off;     // per system: first tile; last entry = total tiles
     const int* sys_rows;     // per system: number of rows
     GridBarrier* bar;        // per system
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(BS) void k_batch(BatchArgs a)
     t.limit = a.limit;
     t.s_flag = &s_flag;
     const int t0 = a.tile_off[sys], nt = a.tile_off[sys + 1] - t0;
-    const TileMap tm{a.tiles + t0, nt, (nt + t.G - 1) / t.G};
+    const TileMap tm{a.tiles + t0, nt, (nt + t.G - 1) / t.G, a.col16};
     SysView<double> v{0, a.rowptr, a.col, a.val, a.dinv, a.b, a.x, a.r, a.z, a.p0, a.p1, a.q};
     const int maxit = a.maxit > 0 ? a.maxit : a.sys_rows[sys];
     double* wprod = prod + (threadIdx.x / kWave) * (kWave * NPL);
@@ -121,6 +122,7 @@ struct cg_batch {
     double* vec = nullptr;  // b, x, r, z, p0, p1, q: 7 N_total
     int2* block_team = nullptr;
     int4* tiles = nullptr;
+    unsigned short* col16 = nullptr;
     int* ints = nullptr;    // team_size, part_off, sys_rows, tile_off
     jpcg::GridBarrier* bar = nullptr;
     double* part = nullptr;
@@ -141,8 +143,8 @@ static void free_batch(cg_batch* b)
 {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    void* ptrs[] = {b->rowptr, b->col, b->val, b->dinv, b->vec, b->block_team, b->tiles, b->ints, b->bar, b->part,
-                    b->info};
+    void* ptrs[] = {b->rowptr, b->col, b->val, b->dinv, b->vec, b->block_team, b->tiles, b->col16, b->ints, b->bar,
+                    b->part, b->info};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (b->hinfo) (void)hipHostFree(b->hinfo);
@@ -204,6 +206,7 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
     if (opts) o = *opts; else cg_opts_default(&o);
     if (o.precond == CG_PRECOND_DEFAULT) o.precond = CG_PRECOND_JACOBI;
     if (o.precond != CG_PRECOND_JACOBI && o.precond != CG_PRECOND_NONE) return CG_EINVAL;
+    if (o.col_bits != 0 && o.col_bits != 32) return CG_EINVAL;
     if (o.autotune) {
         // Build the batch at each tile width, time 20 iterations of every
         // system (tol 0, b = 1) and keep the fastest.
@@ -421,6 +424,7 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
             free_batch(b);
             return CG_EDIAG;
         }
+        if (o.col_bits != 32) b->col16 = make_col16(st, b->tiles, ntile_total, b->col, b->nnz_total);
         double* v = b->vec;
         BatchArgs& a = b->args;
         a.rowptr = b->rowptr;
@@ -438,6 +442,7 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         a.team_size = d_team;
         a.part_off = d_poff;
         a.tiles = b->tiles;
+        a.col16 = b->col16;
         a.tile_off = d_toff;
         a.sys_rows = d_rows;
         a.bar = b->bar;

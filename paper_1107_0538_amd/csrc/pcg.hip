@@ -227,6 +227,7 @@ struct cg_graphs {
     bool fp32 = false;
     int npl = 0, bs = 0, G = 0, T = 0, chunk = 0;
     int4* tiles = nullptr;
+    unsigned short* col16 = nullptr;  // narrow column indices of these tiles (null: 32-bit)
     double* part = nullptr;  // 11G doubles, laid out per form
     void* st = nullptr;      // CgState or SrState
     void* hst = nullptr;     // pinned, 4 slots
@@ -250,7 +251,7 @@ static void destroy_graphs(cg_graphs* g)
         if (e) (void)hipGraphExecDestroy(e);
     for (auto& e : g->evs)
         if (e) (void)hipEventDestroy(e);
-    void* ptrs[] = {g->tiles, g->part, g->st, g->cb, g->cx, g->work32};
+    void* ptrs[] = {g->tiles, g->col16, g->part, g->st, g->cb, g->cx, g->work32};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (g->hst) (void)hipHostFree(g->hst);
@@ -302,7 +303,8 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
         for (auto& e : g->evs) JPCG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         if (T) JPCG_HIP(hipMemcpyAsync(g->tiles, tiles.data(), sizeof(int4) * T, hipMemcpyHostToDevice, c->stream));
         JPCG_HIP(hipMemsetAsync(g->st, 0, g->st_bytes, c->stream));
-        const TileMap tm{g->tiles, T, (T + G - 1) / G};
+        if (c->opts.col_bits != 32) g->col16 = make_col16(c->stream, g->tiles, T, c->col, c->nnz);
+        const TileMap tm{g->tiles, T, (T + G - 1) / G, g->col16};
         if (fp32) {
             JPCG_HIP(hipMalloc(&g->work32, sizeof(float) * 5 * (size_t)c->n));
             JPCG_HIP(hipMemsetAsync(g->work32, 0, sizeof(float) * 5 * (size_t)c->n, c->stream));
@@ -807,7 +809,8 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
         if ((c->opts.precond != CG_PRECOND_JACOBI && c->opts.precond != CG_PRECOND_NONE) ||
             (c->opts.nnz_per_lane && !valid_npl(c->opts.nnz_per_lane)) ||
             (c->opts.block_size && !valid_bs(c->opts.block_size)) || c->opts.chunk < 0 || c->opts.blocks_per_cu < 0 ||
-            (c->opts.form != CG_FORM_STANDARD && c->opts.form != CG_FORM_SINGLE_REDUCTION)) {
+            (c->opts.form != CG_FORM_STANDARD && c->opts.form != CG_FORM_SINGLE_REDUCTION) ||
+            (c->opts.col_bits != 0 && c->opts.col_bits != 32)) {
             free_ctx(c);
             return CG_EINVAL;
         }
@@ -1039,6 +1042,7 @@ int cg_get_config(cg_ctx* c, cg_config* cfg)
     cfg->chunk = c->chunk;
     cfg->form = c->form;
     cfg->tune_cached = c->tune_cached ? 1 : 0;
+    cfg->col_bits = c->graphs && c->graphs->col16 ? 16 : 32;
     cfg->spmv_us = c->tuned_spmv_us;
     cfg->iter_us = c->tuned_iter_us;
     return 0;

@@ -57,7 +57,7 @@ def make_csr(a) -> tuple[capi.cg_csr, list]:
 
 
 def make_opts(precond="jacobi", fp32_copy=False, autotune=False, nnz_per_lane=0, blocks_per_cu=0,
-              history=False, block_size=0, chunk=0, form="standard") -> capi.cg_opts:
+              history=False, block_size=0, chunk=0, form="standard", col_bits=0) -> capi.cg_opts:
     o = capi.cg_opts()
     capi.load().cg_opts_default(ctypes.byref(o))
     o.precond = {"jacobi": capi.CG_PRECOND_JACOBI, "none": capi.CG_PRECOND_NONE}[precond]
@@ -69,6 +69,7 @@ def make_opts(precond="jacobi", fp32_copy=False, autotune=False, nnz_per_lane=0,
     o.block_size = int(block_size)
     o.chunk = int(chunk)
     o.form = capi.FORMS[form]
+    o.col_bits = int(col_bits)
     return o
 
 
@@ -76,7 +77,8 @@ class Solver:
     """A cg_ctx: one SPD CSR matrix resident on the GPU."""
 
     def __init__(self, a, precond="jacobi", fp32_copy=False, autotune=False, nnz_per_lane=0,
-                 blocks_per_cu=0, history=False, block_size=0, chunk=0, form="standard", stream=None):
+                 blocks_per_cu=0, history=False, block_size=0, chunk=0, form="standard", col_bits=0,
+                 stream=None):
         torch = _torch()
         self._lib = capi.load()
         self.n = int(a.n)
@@ -84,7 +86,7 @@ class Solver:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         csr, _keep = make_csr(a)
         opts = make_opts(precond, fp32_copy, autotune, nnz_per_lane, blocks_per_cu, history, block_size, chunk,
-                         form)
+                         form, col_bits)
         ctx = ctypes.c_void_p()
         rc = self._lib.cg_create(ctypes.byref(csr), ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(ctx))
@@ -214,7 +216,8 @@ class Solver:
 class Batch:
     """A cg_batch: many independent SPD CSR systems solved in one launch."""
 
-    def __init__(self, systems, precond="jacobi", nnz_per_lane=0, blocks_per_cu=0, autotune=False, stream=None):
+    def __init__(self, systems, precond="jacobi", nnz_per_lane=0, blocks_per_cu=0, autotune=False, col_bits=0,
+                 stream=None):
         torch = _torch()
         self._lib = capi.load()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
@@ -227,7 +230,8 @@ class Batch:
                 raise ValueError("batched systems must be host (numpy) CSR matrices")
             arr[i] = csr
             self._keep.append(keep)
-        opts = make_opts(precond, autotune=autotune, nnz_per_lane=nnz_per_lane, blocks_per_cu=blocks_per_cu)
+        opts = make_opts(precond, autotune=autotune, nnz_per_lane=nnz_per_lane, blocks_per_cu=blocks_per_cu,
+                         col_bits=col_bits)
         h = ctypes.c_void_p()
         rc = self._lib.cg_batch_create(self.nsys, arr, ctypes.byref(opts), ctypes.c_void_p(self.stream.cuda_stream),
                                        ctypes.byref(h))

@@ -148,3 +148,33 @@ def test_batch_single_and_tiny_systems(cuda):
     assert infos[0]["status"] == infos[2]["status"] == 0
     assert abs(x[0] - 2.0) <= 1e-15 and abs(x[-1] + 3.0) <= 1e-15
     check_system(a, b, x[1:-1], infos[1])
+
+
+def test_batch_column_index_widths(cuda):
+    # 16-bit column offsets give bitwise the 32-bit results; a system whose
+    # columns lie too far from its tiles' first rows falls back to 32 bits.
+    import scipy.sparse as sp
+
+    from paper_1107_0538_amd import Batch
+
+    sys = small_batch(8, seed=5)
+    b_cat = np.concatenate([b for _, b in sys])
+    xs = []
+    for bits in (0, 32):
+        bt = Batch([a for a, _ in sys], col_bits=bits)
+        x, infos = bt.solve(_t(b_cat, cuda))
+        xs.append((x.cpu().numpy(), [i["iters"] for i in infos]))
+    assert np.array_equal(xs[0][0], xs[1][0]) and xs[0][1] == xs[1][1]
+    n = 40000
+    m = sp.diags([np.full(n - 1, -1.0), np.full(n, 2.5), np.full(n - 1, -1.0)], [-1, 0, 1], format="lil")
+    m[0, 32768] = m[32768, 0] = -0.25
+    m = m.tocsr()
+    m.sort_indices()
+    wide = W.CSR(n, m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.astype(np.float64))
+    bw = np.random.default_rng(6).uniform(-1, 1, n)
+    sys2 = sys[:3] + [(wide, bw)]
+    bt = Batch([a for a, _ in sys2])
+    x, infos = bt.solve(_t(np.concatenate([b for _, b in sys2]), cuda))
+    x = x.cpu().numpy()
+    for s, (a, b) in enumerate(sys2):
+        check_system(a, b, x[bt.offsets[s]:bt.offsets[s + 1]], infos[s])

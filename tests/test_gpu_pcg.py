@@ -371,3 +371,55 @@ def test_tiny_systems(cuda, form):
     xo, io = oracle.pcg(two, b, precond="none", form=form)
     assert info["status"] == io["status"] == 0 and info["iters"] == io["iters"] <= 2
     assert np.linalg.norm(x.cpu().numpy() - np.linalg.solve(two.to_dense(), b)) <= 1e-14
+
+
+def linked_tridiagonal(n, link):
+    """Diagonally dominant tridiagonal matrix plus the symmetric pair (0, link):
+    row 0 has a column `link` rows away from the first row of its tile."""
+    import scipy.sparse as sp
+
+    main = np.full(n, 2.5)
+    off = np.full(n - 1, -1.0)
+    m = sp.diags([off, main, off], [-1, 0, 1], format="lil")
+    m[0, link] = m[link, 0] = -0.25
+    m = m.tocsr()
+    m.sort_indices()
+    return W.CSR(n, m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("n", [16, 51])
+def test_column_index_widths_agree(cuda, n, form):
+    # 16-bit column offsets read the same columns: products and solves are
+    # bitwise those of 32-bit columns.
+    from paper_1107_0538_amd import Solver
+
+    a, b = prob(n)
+    x = np.random.default_rng(7).uniform(-1, 1, a.n)
+    out = {}
+    for bits in (0, 32):
+        s = Solver(a, form=form, col_bits=bits)
+        assert s.config()["col_bits"] == (16 if bits == 0 else 32)
+        y = s.spmv(_t(x, cuda)).cpu().numpy()
+        xs, info = s.solve(_t(b, cuda))
+        out[bits] = (y, xs.cpu().numpy(), info["iters"])
+    assert np.array_equal(out[0][0], out[32][0]) and np.array_equal(out[0][0], oracle.spmv(a, x))
+    assert np.array_equal(out[0][1], out[32][1]) and out[0][2] == out[32][2]
+
+
+@pytest.mark.parametrize("link,bits", [(32767, 16), (32768, 32)])
+@pytest.mark.parametrize("npl", [4, 16])
+def test_column_offset_limit(cuda, link, bits, npl):
+    # The largest offset that fits 16 bits, and one past it (32-bit fallback).
+    from paper_1107_0538_amd import Solver
+
+    a = linked_tridiagonal(40000, link)
+    s = Solver(a, nnz_per_lane=npl)
+    assert s.config()["col_bits"] == bits
+    x = np.random.default_rng(8).uniform(-1, 1, a.n)
+    assert np.array_equal(s.spmv(_t(x, cuda)).cpu().numpy(), oracle.spmv(a, x))
+    b = np.random.default_rng(9).uniform(-1, 1, a.n)
+    xg, info = s.solve(_t(b, cuda))
+    xo, io = oracle.pcg(a, b)
+    assert info["status"] == io["status"] == 0 and abs(info["iters"] - io["iters"]) <= 2
+    assert np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-8
