@@ -54,10 +54,10 @@ def solve_bytes(n, nnz, iters, checks, form="standard", vb=8, ib=4):
 
 # HBM bytes per iteration from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a
 # 512 MiB copy: fetch x2, write x1) for the 51^3 system, keyed by form and
-# launch shape (nonzeros per lane, block size).
+# launch shape (nonzeros per lane, block size, column index bits).
 MEASURED_TRAFFIC = {
-    ("standard", 132651, 3442951, 16, 512): 55.73e6,  # k_direction + k_update
-    ("single", 132651, 3442951, 8, 512): 56.39e6,     # k_sr_iter
+    ("standard", 132651, 3442951, 16, 512, 16): 48.79e6,  # k_direction + k_update
+    ("single", 132651, 3442951, 8, 512, 16): 49.30e6,     # k_sr_iter
 }
 
 
@@ -72,12 +72,16 @@ def roofline(form, n, nnz, run):
     per_iter_s = run["device_s"] / max(run["iters"], 1)
     ib = iter_bytes(n, nnz, form)
     launch = run["launch"]
-    traffic = MEASURED_TRAFFIC.get((form, n, nnz, launch["nnz_per_lane"], launch["block_size"]))
+    traffic = MEASURED_TRAFFIC.get((form, n, nnz, launch["nnz_per_lane"], launch["block_size"], launch["col_bits"]))
+    # With 16-bit column offsets the products' compulsory bytes are 2 per
+    # nonzero fewer than the CSR count that `achieved` uses.
+    fb = ib - 2 * nnz if launch.get("col_bits") == 16 else ib
     return {
         "kernel": ("k_sr_iter" if form == "single" else "k_direction + k_update") + " (one CG iteration)",
         "bound": "hbm", "achieved": ib / per_iter_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": ib / per_iter_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
         "bytes_per_launch": ib, "launch_s": per_iter_s,
+        "format_bytes_per_launch": fb, "format_frac": fb / per_iter_s / 1e9 / HBM_PEAK_GBS,
     }
 
 
