@@ -29,11 +29,14 @@ struct cg_ctx {
     float* rowsum32 = nullptr;  // fp32_copy: row sums of A (FP64 sums, FP32 storage)
     std::vector<int> h_rowptr;
 
-    // Work vectors for single-RHS solves (n each, one allocation): the
-    // standard form uses r, z, p (two), q; the single-reduction form uses
-    // r, w, s (two each) and p.
+    // Work vectors for single-RHS solves (one allocation, each vector at a
+    // stride of n rounded up to 64 entries, so every vector and every pair of
+    // vectors starts 512-byte aligned): the standard form uses r, two
+    // interleaved {z, p} pair arrays of two vectors each, and q; the
+    // single-reduction form uses r, w, s (two each) and p.
     static constexpr int kWorkVecs = 7;
     double* work[kWorkVecs] = {};
+    size_t work_stride = 0;
 
     // Graph-chunked solver for the chosen launch shape.
     struct cg_graphs* graphs = nullptr;      // the context's form, FP64

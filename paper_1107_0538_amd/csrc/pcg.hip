@@ -234,7 +234,7 @@ struct cg_graphs {
     size_t st_bytes = 0;
     void* cb = nullptr;      // the solver's own b and x: graphs bind fixed addresses
     void* cx = nullptr;
-    void* work32 = nullptr;  // FP32 work vectors (5n floats)
+    void* work32 = nullptr;  // FP32 work vectors: r, two {z, p} pair arrays, q (6 strides)
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipEvent_t evs[4] = {nullptr, nullptr, nullptr, nullptr};
     jpcg::CgArgsT<double> args{};
@@ -306,21 +306,25 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
         if (c->opts.col_bits != 32) g->col16 = make_col16(c->stream, g->tiles, T, c->col, c->nnz);
         const TileMap tm{g->tiles, T, (T + G - 1) / G, g->col16};
         if (fp32) {
-            JPCG_HIP(hipMalloc(&g->work32, sizeof(float) * 5 * (size_t)c->n));
-            JPCG_HIP(hipMemsetAsync(g->work32, 0, sizeof(float) * 5 * (size_t)c->n, c->stream));
+            const size_t n = c->work_stride;
+            JPCG_HIP(hipMalloc(&g->work32, sizeof(float) * 6 * n));
+            JPCG_HIP(hipMemsetAsync(g->work32, 0, sizeof(float) * 6 * n, c->stream));
             float* w = (float*)g->work32;
-            const size_t n = c->n;
             fill_args(g->args32,
                       SysView<float>{c->n, c->rowptr, c->col, c->val32, c->dinv32, (float*)g->cb, (float*)g->cx, w,
-                                     w + n, w + 2 * n, w + 3 * n, w + 4 * n},
+                                     nullptr, nullptr, nullptr, w + 5 * n},
                       tm, c->n, G, g->part, g->st);
+            g->args32.zp[0] = (ZPair<float>*)(w + n);
+            g->args32.zp[1] = (ZPair<float>*)(w + 3 * n);
             g->args32.rowsum = c->rowsum32;
         } else {
             double* const* w = c->work;
             fill_args(g->args,
                       SysView<double>{c->n, c->rowptr, c->col, c->val, c->dinv, (double*)g->cb, (double*)g->cx, w[0],
-                                      w[1], w[2], w[3], w[4]},
+                                      nullptr, nullptr, nullptr, w[5]},
                       tm, c->n, G, g->part, g->st);
+            g->args.zp[0] = (ZPair<double>*)w[1];  // spans w[1], w[2]
+            g->args.zp[1] = (ZPair<double>*)w[3];  // spans w[3], w[4]
             g->args.rowsum = nullptr;
             SrArgs& sa = g->sargs;
             sa.n = c->n;
@@ -855,9 +859,10 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
         JPCG_HIP(hipMemsetAsync(c->col + nnz, 0, sizeof(int) * kCsrPad, c->stream));
         JPCG_HIP(hipMemsetAsync(c->val + nnz, 0, sizeof(double) * kCsrPad, c->stream));
         JPCG_HIP(hipMalloc(&c->dinv, sizeof(double) * n));
-        JPCG_HIP(hipMalloc(&c->work[0], sizeof(double) * (size_t)n * cg_ctx::kWorkVecs));
-        for (int v = 1; v < cg_ctx::kWorkVecs; ++v) c->work[v] = c->work[0] + (size_t)v * n;
-        JPCG_HIP(hipMemsetAsync(c->work[0], 0, sizeof(double) * (size_t)n * cg_ctx::kWorkVecs, c->stream));
+        c->work_stride = ((size_t)n + 63) / 64 * 64;
+        JPCG_HIP(hipMalloc(&c->work[0], sizeof(double) * c->work_stride * cg_ctx::kWorkVecs));
+        for (int v = 1; v < cg_ctx::kWorkVecs; ++v) c->work[v] = c->work[0] + (size_t)v * c->work_stride;
+        JPCG_HIP(hipMemsetAsync(c->work[0], 0, sizeof(double) * c->work_stride * cg_ctx::kWorkVecs, c->stream));
         JPCG_HIP(hipEventCreate(&c->ev0));
         JPCG_HIP(hipEventCreate(&c->ev1));
         JPCG_HIP(hipMemcpyAsync(c->rowptr, rp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, c->stream));

@@ -10,6 +10,11 @@
 //   B_k  (k_update)  reduce A_k's partials, alpha_k = rho_{k-1} / sigma_k;
 //        x += alpha p, r -= alpha q, z = M^-1 r; partials of r'z and r'r.
 //
+// z and p are stored interleaved, ZPair {z_i, p_i} per row, in two arrays used
+// by iteration parity: zp[P] holds {z_k, p_k} once B_k has run (A_k writes p_k
+// into zp[P].p, B_k writes z_k into zp[P].z), so A_{k+1} fetches both operands
+// of p_{k+1} = z_k + beta p_k for a column with one 2-element load.
+//
 // Every workgroup reduces the previous kernel's per-workgroup partials itself,
 // in a fixed order, so all workgroups reach the same bits and the same
 // decision without atomics.  Scalars that must outlive a kernel sit in a small
@@ -36,8 +41,14 @@ struct CgState {
 };
 
 template <typename T>
+struct alignas(2 * sizeof(T)) ZPair {
+    T z, p;
+};
+
+template <typename T>
 struct CgArgsT {
-    SysView<T> s;  // b, x are the solver's own buffers; p0/p1 alternate by parity
+    SysView<T> s;  // b, x, r, q: the solver's own buffers (z, p0, p1 unused: see zp)
+    ZPair<T>* zp[2];  // by parity: {z, p} per row
     const T* rowsum;  // FP32 solves: row sums of A (computed in FP64) for the row-sum-preserving product
     TileMap tm;    // tiles of the sparse products, per workgroup
     int R;         // rows per workgroup of the elementwise update
@@ -85,15 +96,10 @@ struct Tri {
 
 __device__ __forceinline__ int logical_of(int G) { return xcd_logical_block((int)blockIdx.x, G); }
 
-template <typename T>
-struct PairT {
-    T a, b;
-};
-
-// r_out = b - A x and (if z_out) z_out = M^-1 r_out over the workgroup's tiles;
-// shares of r'r, r'z, b'b.
+// r_out = b - A x and (if z_out) z_out[i].z = M^-1 r_out over the workgroup's
+// tiles; shares of r'r, r'z, b'b.
 template <int NPL, int BS, typename T>
-__device__ __forceinline__ void tile_residual(const CgArgsT<T>& a, T* prod, T* r_out, T* z_out, double& rr,
+__device__ __forceinline__ void tile_residual(const CgArgsT<T>& a, T* prod, T* r_out, ZPair<T>* z_out, double& rr,
                                               double& rz, double& bb)
 {
     const SysView<T>& s = a.s;
@@ -109,7 +115,7 @@ __device__ __forceinline__ void tile_residual(const CgArgsT<T>& a, T* prod, T* r
             bb += (double)bi * (double)bi;
             if (z_out) {
                 const T zi = bd.b * ri;
-                z_out[i] = zi;
+                z_out[i].z = zi;
                 rz += (double)ri * (double)zi;
             }
         },
@@ -121,11 +127,11 @@ __global__ __launch_bounds__(BS) void k_setup(CgArgsT<T> a)
 {
     __shared__ Lds<NPL, BS, T> sh;
     double v[3] = {0.0, 0.0, 0.0};
-    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.s.z, v[0], v[1], v[2]);
+    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.zp[0], v[0], v[1], v[2]);
     block_partials<BS, 3>(v, sh.red, a.part_setup, logical_of(a.G));
 }
 
-// A_1: initial tests, then p_1 = z_0, q = A p_1.
+// A_1: initial tests, then p_1 = z_0 (from zp[0].z), q = A p_1, p_1 into zp[1].p.
 template <int NPL, int BS, typename T>
 __global__ __launch_bounds__(BS) void k_first(CgArgsT<T> a, double tol, int maxit)
 {
@@ -156,13 +162,14 @@ __global__ __launch_bounds__(BS) void k_first(CgArgsT<T> a, double tol, int maxi
         return;
     }
     if (sqrt(rr) <= thr) return;
-    const T* __restrict__ z = s.z;
+    const ZPair<T>* __restrict__ z0 = a.zp[0];
+    ZPair<T>* __restrict__ p1 = a.zp[1];
     double sig = 0.0;
     walk<NPL, T>(
-        s, a.rowsum, a.tm, L, sh.prod, [&](int j) { return z[j]; }, Ident<T>{}, [&](int i) { return z[i]; },
+        s, a.rowsum, a.tm, L, sh.prod, [&](int j) { return z0[j].z; }, Ident<T>{}, [&](int i) { return z0[i].z; },
         [&](T zi) { return zi; },
         [&](int i, T qi, T pi) {
-            s.p1[i] = pi;
+            p1[i] = ZPair<T>{T(0), pi};  // whole pair: .z is written by B_1
             s.q[i] = qi;
             sig += (double)pi * (double)qi;
         },
@@ -180,9 +187,8 @@ __global__ __launch_bounds__(BS) void k_direction(CgArgsT<T> a, int P)
     __shared__ Lds<NPL, BS, T> sh;
     CgState* st = a.st;
     const SysView<T>& s = a.s;
-    const T* __restrict__ z = s.z;
-    const T* __restrict__ pold = P ? s.p0 : s.p1;
-    T* __restrict__ pnew = P ? s.p1 : s.p0;
+    const ZPair<T>* __restrict__ zpold = a.zp[P ^ 1];  // {z_{k-1}, p_{k-1}}
+    ZPair<T>* __restrict__ zpnew = a.zp[P];
     const int L = logical_of(a.G);
     const bool lead = threadIdx.x == 0 && L == 0;
     T beta = T(0);
@@ -223,12 +229,12 @@ __global__ __launch_bounds__(BS) void k_direction(CgArgsT<T> a, int P)
         return true;
     };
     walk<NPL, T>(
-        s, a.rowsum, a.tm, L, sh.prod, [&](int j) { return PairT<T>{z[j], pold[j]}; },
-        [&](PairT<T> zp) { return fma_t(beta, zp.b, zp.a); }, [&](int i) { return PairT<T>{z[i], pold[i]}; },
-        [&](PairT<T> zp) { return fma_t(beta, zp.b, zp.a); },
-        [&](int i, T qi, PairT<T> zp) {
-            const T pi = fma_t(beta, zp.b, zp.a);
-            pnew[i] = pi;
+        s, a.rowsum, a.tm, L, sh.prod, [&](int j) { return zpold[j]; },
+        [&](ZPair<T> zp) { return fma_t(beta, zp.p, zp.z); }, [&](int i) { return zpold[i]; },
+        [&](ZPair<T> zp) { return fma_t(beta, zp.p, zp.z); },
+        [&](int i, T qi, ZPair<T> zp) {
+            const T pi = fma_t(beta, zp.p, zp.z);
+            zpnew[i] = ZPair<T>{T(0), pi};  // whole pair: .z (z_{k-2}) is dead until B_k
             s.q[i] = qi;
             sig += (double)pi * (double)qi;
         },
@@ -250,11 +256,12 @@ __global__ __launch_bounds__(BS) void k_update(CgArgsT<T> a, int P)
     const double rho = st->rho[P];
     const int L = logical_of(a.G);
     const int rs = min(L * a.R, s.n), re = min(rs + a.R, s.n);
-    const T* __restrict__ p = P ? s.p1 : s.p0;
+    ZPair<T>* __restrict__ zp = a.zp[P];  // p_k in .p; z_k goes to .z
     const int i0 = rs + (int)threadIdx.x;
     const bool h0 = i0 < re;
     const int ic = h0 ? i0 : 0;
-    const T p0 = p[ic], q0 = s.q[ic], x0 = s.x[ic], r0 = s.r[ic], d0 = s.dinv[ic];
+    const T p0 = zp[ic].p, q0 = s.q[ic], x0 = s.x[ic], r0 = s.r[ic], d0 = s.dinv[ic];
+    // z_k is written with p_k as a whole pair (full 2-element stores).
     double g[1];
     wave_grid_sum<1>(a.part_sig, a.G, g);
     const double sigma = g[0];
@@ -272,16 +279,17 @@ __global__ __launch_bounds__(BS) void k_update(CgArgsT<T> a, int P)
         const T ri = fma_t(-alpha, q0, r0);
         s.r[i0] = ri;
         const T zi = d0 * ri;
-        s.z[i0] = zi;
+        zp[i0] = ZPair<T>{zi, p0};
         v[0] += (double)ri * (double)zi;
         v[1] += (double)ri * (double)ri;
     }
     for (int i = i0 + BS; i < re; i += BS) {
-        s.x[i] = fma_t(alpha, p[i], s.x[i]);
+        const T pi = zp[i].p;
+        s.x[i] = fma_t(alpha, pi, s.x[i]);
         const T ri = fma_t(-alpha, s.q[i], s.r[i]);
         s.r[i] = ri;
         const T zi = s.dinv[i] * ri;
-        s.z[i] = zi;
+        zp[i] = ZPair<T>{zi, pi};
         v[0] += (double)ri * (double)zi;
         v[1] += (double)ri * (double)ri;
     }
@@ -293,13 +301,14 @@ __global__ __launch_bounds__(BS) void k_update(CgArgsT<T> a, int P)
     }
 }
 
-// True residual r = b - A x, z = M^-1 r into the slot the next A_{k+1} reads.
+// True residual r = b - A x, z = M^-1 r into zp[P].z, the slot A_{k+1} reads
+// (p_k in zp[P].p is kept).
 template <int NPL, int BS, typename T>
 __global__ __launch_bounds__(BS) void k_check(CgArgsT<T> a, int P)
 {
     __shared__ Lds<NPL, BS, T> sh;
     double rr = 0.0, rz = 0.0, bb = 0.0;
-    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.s.z, rr, rz, bb);
+    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.zp[P], rr, rz, bb);
     double v[2] = {rz, rr};
     block_partials<BS, 2>(v, sh.red, a.part_iter[P], logical_of(a.G));
 }
@@ -329,7 +338,7 @@ __global__ __launch_bounds__(BS) void k_report(CgArgsT<T> a)
     __shared__ Lds<NPL, BS, T> sh;
     double v[1] = {0.0};
     double rz = 0.0, bb = 0.0;
-    tile_residual<NPL, BS, T>(a, sh.prod, a.s.q, (T*)nullptr, v[0], rz, bb);
+    tile_residual<NPL, BS, T>(a, sh.prod, a.s.q, (ZPair<T>*)nullptr, v[0], rz, bb);
     block_partials<BS, 1>(v, sh.red, a.part_rep, logical_of(a.G));
 }
 
