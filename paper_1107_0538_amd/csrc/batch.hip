@@ -31,9 +31,7 @@ struct BatchArgs {
     const double* b;
     double* x;
     double* r;
-    double* z;
-    double* p0;
-    double* p1;
+    ZPair<double>* zp[2];  // {z, p} per row by iteration parity
     double* q;
     const int2* block_team;  // per workgroup: (system, member)
     const int* team_size;    // per system
@@ -50,8 +48,11 @@ struct BatchArgs {
     long long limit;
 };
 
+// At least three waves per SIMD: at tile width 16 the kernel would otherwise
+// take a few more registers than that allows and run two workgroups per CU
+// instead of three (about 8 % slower on the 256-system batch).
 template <int NPL, int BS>
-__global__ __launch_bounds__(BS) void k_batch(BatchArgs a)
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3))) void k_batch(BatchArgs a)
 {
     __shared__ double lds[(BS / kWave) * 4];
     __shared__ double prod[BS * NPL];
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(BS) void k_batch(BatchArgs a)
     t.s_flag = &s_flag;
     const int t0 = a.tile_off[sys], nt = a.tile_off[sys + 1] - t0;
     const TileMap tm{a.tiles + t0, nt, (nt + t.G - 1) / t.G, a.col16};
-    SysView<double> v{0, a.rowptr, a.col, a.val, a.dinv, a.b, a.x, a.r, a.z, a.p0, a.p1, a.q};
+    SysView<double> v{0, a.rowptr, a.col, a.val, a.dinv, a.b, a.x, a.r, {a.zp[0], a.zp[1]}, a.q};
     const int maxit = a.maxit > 0 ? a.maxit : a.sys_rows[sys];
     double* wprod = prod + (threadIdx.x / kWave) * (kWave * NPL);
     const int st = pcg_team<NPL, BS, double>(v, t, tm, wprod, a.tol, maxit, lds, a.info + sys, nullptr);
@@ -119,7 +120,7 @@ struct cg_batch {
     int* col = nullptr;
     double* val = nullptr;
     double* dinv = nullptr;
-    double* vec = nullptr;  // b, x, r, z, p0, p1, q: 7 N_total
+    double* vec = nullptr;  // b, x, r, {z, p} pairs (two), q: 8 strides of N_total rounded up to 64
     int2* block_team = nullptr;
     int4* tiles = nullptr;
     unsigned short* col16 = nullptr;
@@ -382,7 +383,8 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         JPCG_HIP(hipMalloc(&b->col, sizeof(int) * std::max<int64_t>(b->nnz_total, 1)));
         JPCG_HIP(hipMalloc(&b->val, sizeof(double) * std::max<int64_t>(b->nnz_total, 1)));
         JPCG_HIP(hipMalloc(&b->dinv, sizeof(double) * N));
-        JPCG_HIP(hipMalloc(&b->vec, sizeof(double) * 7 * (size_t)N));
+        const size_t NP = ((size_t)N + 63) / 64 * 64;
+        JPCG_HIP(hipMalloc(&b->vec, sizeof(double) * 8 * NP));
         JPCG_HIP(hipMalloc(&b->block_team, sizeof(int2) * used));
         JPCG_HIP(hipMalloc(&b->tiles, sizeof(int4) * std::max(ntile_total, 1)));
         JPCG_HIP(hipMalloc(&b->ints, sizeof(int) * (4 * (size_t)nsys + 1)));
@@ -398,7 +400,7 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         for (int s = 0; s < nsys; ++s)
             JPCG_HIP(hipMemcpyAsync(b->val + nnz_off[s], systems[s].val, sizeof(double) * systems[s].nnz,
                                     hipMemcpyHostToDevice, st));
-        JPCG_HIP(hipMemsetAsync(b->vec, 0, sizeof(double) * 7 * (size_t)N, st));
+        JPCG_HIP(hipMemsetAsync(b->vec, 0, sizeof(double) * 8 * NP, st));
         JPCG_HIP(hipMemcpyAsync(b->block_team, block_team.data(), sizeof(int2) * used, hipMemcpyHostToDevice, st));
         int* d_team = b->ints;
         int* d_poff = d_team + nsys;
@@ -432,12 +434,11 @@ int cg_batch_create(int32_t nsys, const cg_csr* systems, const cg_opts* opts, vo
         a.val = b->val;
         a.dinv = b->dinv;
         a.b = v;
-        a.x = v + (size_t)N;
-        a.r = v + 2 * (size_t)N;
-        a.z = v + 3 * (size_t)N;
-        a.p0 = v + 4 * (size_t)N;
-        a.p1 = v + 5 * (size_t)N;
-        a.q = v + 6 * (size_t)N;
+        a.x = v + NP;
+        a.r = v + 2 * NP;
+        a.zp[0] = (ZPair<double>*)(v + 3 * NP);  // spans strides 3 and 4
+        a.zp[1] = (ZPair<double>*)(v + 5 * NP);  // spans strides 5 and 6
+        a.q = v + 7 * NP;
         a.block_team = b->block_team;
         a.team_size = d_team;
         a.part_off = d_poff;

@@ -312,19 +312,16 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
             float* w = (float*)g->work32;
             fill_args(g->args32,
                       SysView<float>{c->n, c->rowptr, c->col, c->val32, c->dinv32, (float*)g->cb, (float*)g->cx, w,
-                                     nullptr, nullptr, nullptr, w + 5 * n},
+                                     {(ZPair<float>*)(w + n), (ZPair<float>*)(w + 3 * n)}, w + 5 * n},
                       tm, c->n, G, g->part, g->st);
-            g->args32.zp[0] = (ZPair<float>*)(w + n);
-            g->args32.zp[1] = (ZPair<float>*)(w + 3 * n);
             g->args32.rowsum = c->rowsum32;
         } else {
             double* const* w = c->work;
             fill_args(g->args,
                       SysView<double>{c->n, c->rowptr, c->col, c->val, c->dinv, (double*)g->cb, (double*)g->cx, w[0],
-                                      nullptr, nullptr, nullptr, w[5]},
+                                      {(ZPair<double>*)w[1], (ZPair<double>*)w[3]},  // spanning w[1..2], w[3..4]
+                                      w[5]},
                       tm, c->n, G, g->part, g->st);
-            g->args.zp[0] = (ZPair<double>*)w[1];  // spans w[1], w[2]
-            g->args.zp[1] = (ZPair<double>*)w[3];  // spans w[3], w[4]
             g->args.rowsum = nullptr;
             SrArgs& sa = g->sargs;
             sa.n = c->n;

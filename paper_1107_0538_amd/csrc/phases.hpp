@@ -56,6 +56,15 @@ struct DevInfo {
     double pad;
 };
 
+// z and p of the CG loop, stored interleaved per row in two arrays used by
+// iteration parity: the product fetches both operands of p_new = z + beta
+// p_old for a column with one 2-element load.  Stores write whole pairs
+// where they can (a dead half gets 0 or its current value).
+template <typename T>
+struct alignas(2 * sizeof(T)) ZPair {
+    T z, p;
+};
+
 template <typename T>
 struct SysView {
     int n;
@@ -66,9 +75,7 @@ struct SysView {
     const T* b;
     T* x;
     T* r;
-    T* z;
-    T* p0;
-    T* p1;
+    ZPair<T>* zp[2];  // by parity: {z, p} per row
     T* q;
 };
 
@@ -105,11 +112,6 @@ __device__ __forceinline__ float fma_t<float>(float a, float b, float c)
 }
 
 template <typename T>
-struct ZP {
-    T z, p;
-};
-
-template <typename T>
 struct BD {
     T b, d;
 };
@@ -123,32 +125,32 @@ __device__ __forceinline__ int2 tile_row_range(const TileMap& tm, int L)
 }
 
 // Step A: p_new = z + beta p_old (or z on the first step), q = A p_new over the
-// workgroup's tiles, p_new formed on the fly in the gather.  Returns this
-// thread's share of p_new' q.
+// workgroup's tiles, p_new formed on the fly in the gather of {z, p_old} from
+// `cur` and stored into `nxt` (whose z half is dead until step B).  Returns
+// this thread's share of p_new' q.
 template <int NPL, typename T>
 __device__ __forceinline__ double step_a(const SysView<T>& s, const TileMap& tm, int L, T* prod, bool first, T beta,
-                                         const T* __restrict__ pold, T* __restrict__ pnew)
+                                         const ZPair<T>* __restrict__ cur, ZPair<T>* __restrict__ nxt)
 {
-    const T* __restrict__ z = s.z;
     T* __restrict__ q = s.q;
     double sig = 0.0;
     if (first) {
         tile_rows<NPL, T>(
-            s.rowptr, s.col, s.val, tm, L, prod, [&](int j) { return z[j]; }, Ident<T>{},
-            [&](int i) { return z[i]; },
+            s.rowptr, s.col, s.val, tm, L, prod, [&](int j) { return cur[j].z; }, Ident<T>{},
+            [&](int i) { return cur[i].z; },
             [&](int i, T qi, T pi) {
-                pnew[i] = pi;
+                nxt[i] = ZPair<T>{T(0), pi};
                 q[i] = qi;
                 sig += (double)pi * (double)qi;
             },
             NoPrologue{});
     } else {
         tile_rows<NPL, T>(
-            s.rowptr, s.col, s.val, tm, L, prod, [&](int j) { return ZP<T>{z[j], pold[j]}; },
-            [&](ZP<T> g) { return fma_t(beta, g.p, g.z); }, [&](int i) { return ZP<T>{z[i], pold[i]}; },
-            [&](int i, T qi, ZP<T> o) {
+            s.rowptr, s.col, s.val, tm, L, prod, [&](int j) { return cur[j]; },
+            [&](ZPair<T> g) { return fma_t(beta, g.p, g.z); }, [&](int i) { return cur[i]; },
+            [&](int i, T qi, ZPair<T> o) {
                 const T pi = fma_t(beta, o.p, o.z);
-                pnew[i] = pi;
+                nxt[i] = ZPair<T>{T(0), pi};
                 q[i] = qi;
                 sig += (double)pi * (double)qi;
             },
@@ -157,28 +159,29 @@ __device__ __forceinline__ double step_a(const SysView<T>& s, const TileMap& tm,
     return sig;
 }
 
-// Step B: x += alpha p, r -= alpha q, z = M^-1 r; shares of r'z and r'r.
+// Step B: x += alpha p, r -= alpha q, z = M^-1 r with p and z in `zp`; shares
+// of r'z and r'r.
 template <int BS, typename T>
-__device__ __forceinline__ void step_b(const SysView<T>& s, int rs, int re, T alpha, const T* __restrict__ p,
+__device__ __forceinline__ void step_b(const SysView<T>& s, int rs, int re, T alpha, ZPair<T>* __restrict__ zp,
                                        double& rz, double& rr)
 {
     for (int i = rs + (int)threadIdx.x; i < re; i += BS) {
-        const T pi = p[i], qi = s.q[i];
+        const T pi = zp[i].p, qi = s.q[i];
         s.x[i] = fma_t(alpha, pi, s.x[i]);
         const T ri = fma_t(-alpha, qi, s.r[i]);
         s.r[i] = ri;
         const T zi = s.dinv[i] * ri;
-        s.z[i] = zi;
+        zp[i] = ZPair<T>{zi, pi};
         rz += (double)ri * (double)zi;
         rr += (double)ri * (double)ri;
     }
 }
 
-// Step R: rout = b - A x and, if zout, zout = M^-1 rout over the workgroup's
-// tiles; shares of r'r, r'z, b'b.
+// Step R: rout = b - A x and, if zout, zout[i].z = M^-1 rout over the
+// workgroup's tiles; shares of r'r, r'z, b'b.
 template <int NPL, typename T>
 __device__ __forceinline__ void step_r(const SysView<T>& s, const TileMap& tm, int L, T* prod, T* __restrict__ rout,
-                                       T* __restrict__ zout, double& rr, double& rz, double& bb)
+                                       ZPair<T>* __restrict__ zout, double& rr, double& rz, double& bb)
 {
     const T* __restrict__ x = s.x;
     tile_rows<NPL, T>(
@@ -191,7 +194,7 @@ __device__ __forceinline__ void step_r(const SysView<T>& s, const TileMap& tm, i
             bb += (double)o.b * (double)o.b;
             if (zout) {
                 const T zi = o.d * ri;
-                zout[i] = zi;
+                zout[i].z = zi;
                 rz += (double)ri * (double)zi;
             }
         },
@@ -215,7 +218,7 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, const TileMap& tm, T* prod
 
     {   // r0 = b - A x0, z0 = M^-1 r0, ||b||^2, ||r0||^2, r0'z0
         double v[3] = {0.0, 0.0, 0.0};
-        step_r<NPL, T>(s, tm, t.L, prod, s.r, s.z, v[0], v[1], v[2]);
+        step_r<NPL, T>(s, tm, t.L, prod, s.r, s.zp[0], v[0], v[1], v[2]);
         block_partials<BS, 3>(v, lds, t.slot(SLOT_SETUP), t.L);
     }
     if (!t.sync()) return CG_ETIMEOUT;
@@ -251,10 +254,11 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, const TileMap& tm, T* prod
 
     double beta = 0.0;
     while (k < maxit) {
-        const T* pold = (k & 1) ? s.p1 : s.p0;
-        T* pnew = (k & 1) ? s.p0 : s.p1;
+        // zp[k & 1] holds {z_k, p_k}; p_{k+1} and then z_{k+1} go to the other.
+        const ZPair<T>* cur = (k & 1) ? s.zp[1] : s.zp[0];  // selects, not a dynamic index: s is local
+        ZPair<T>* nxt = (k & 1) ? s.zp[0] : s.zp[1];
         {
-            double v[1] = {step_a<NPL, T>(s, tm, t.L, prod, k == 0, (T)beta, pold, pnew)};
+            double v[1] = {step_a<NPL, T>(s, tm, t.L, prod, k == 0, (T)beta, cur, nxt)};
             block_partials<BS, 1>(v, lds, t.slot(SLOT_SIG), t.L);
         }
         if (!t.sync()) return CG_ETIMEOUT;
@@ -271,7 +275,7 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, const TileMap& tm, T* prod
         const double alpha = rho / sigma;
         {
             double v[2] = {0.0, 0.0};
-            step_b<BS, T>(s, rs, re, (T)alpha, pnew, v[0], v[1]);
+            step_b<BS, T>(s, rs, re, (T)alpha, nxt, v[0], v[1]);
             block_partials<BS, 2>(v, lds, t.slot(SLOT_ITER), t.L);
         }
         ++k;
@@ -288,7 +292,7 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, const TileMap& tm, T* prod
             // Continue-condition met on the recurrence: confirm on b - A x.
             {
                 double v[2] = {0.0, 0.0}, unused = 0.0;
-                step_r<NPL, T>(s, tm, t.L, prod, s.r, s.z, v[0], v[1], unused);
+                step_r<NPL, T>(s, tm, t.L, prod, s.r, (k & 1) ? s.zp[1] : s.zp[0], v[0], v[1], unused);
                 block_partials<BS, 2>(v, lds, t.slot(SLOT_CHECK), t.L);
             }
             if (!t.sync()) return CG_ETIMEOUT;
@@ -312,7 +316,7 @@ __device__ int pcg_team(const SysView<T>& s, Team& t, const TileMap& tm, T* prod
 
     if (rrt < 0.0) {  // report the true residual of the returned x
         double v[1] = {0.0}, unused0 = 0.0, unused1 = 0.0;
-        step_r<NPL, T>(s, tm, t.L, prod, s.q, (T*)nullptr, v[0], unused0, unused1);
+        step_r<NPL, T>(s, tm, t.L, prod, s.q, (ZPair<T>*)nullptr, v[0], unused0, unused1);
         block_partials<BS, 1>(v, lds, t.slot(SLOT_CHECK), t.L);
         if (!t.sync()) return CG_ETIMEOUT;
         double g[1];

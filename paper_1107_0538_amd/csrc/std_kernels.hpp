@@ -41,14 +41,8 @@ struct CgState {
 };
 
 template <typename T>
-struct alignas(2 * sizeof(T)) ZPair {
-    T z, p;
-};
-
-template <typename T>
 struct CgArgsT {
-    SysView<T> s;  // b, x, r, q: the solver's own buffers (z, p0, p1 unused: see zp)
-    ZPair<T>* zp[2];  // by parity: {z, p} per row
+    SysView<T> s;  // b, x: the solver's own buffers; zp[P] as described above
     const T* rowsum;  // FP32 solves: row sums of A (computed in FP64) for the row-sum-preserving product
     TileMap tm;    // tiles of the sparse products, per workgroup
     int R;         // rows per workgroup of the elementwise update
@@ -127,7 +121,7 @@ __global__ __launch_bounds__(BS) void k_setup(CgArgsT<T> a)
 {
     __shared__ Lds<NPL, BS, T> sh;
     double v[3] = {0.0, 0.0, 0.0};
-    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.zp[0], v[0], v[1], v[2]);
+    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.s.zp[0], v[0], v[1], v[2]);
     block_partials<BS, 3>(v, sh.red, a.part_setup, logical_of(a.G));
 }
 
@@ -162,8 +156,8 @@ __global__ __launch_bounds__(BS) void k_first(CgArgsT<T> a, double tol, int maxi
         return;
     }
     if (sqrt(rr) <= thr) return;
-    const ZPair<T>* __restrict__ z0 = a.zp[0];
-    ZPair<T>* __restrict__ p1 = a.zp[1];
+    const ZPair<T>* __restrict__ z0 = a.s.zp[0];
+    ZPair<T>* __restrict__ p1 = a.s.zp[1];
     double sig = 0.0;
     walk<NPL, T>(
         s, a.rowsum, a.tm, L, sh.prod, [&](int j) { return z0[j].z; }, Ident<T>{}, [&](int i) { return z0[i].z; },
@@ -187,8 +181,8 @@ __global__ __launch_bounds__(BS) void k_direction(CgArgsT<T> a, int P)
     __shared__ Lds<NPL, BS, T> sh;
     CgState* st = a.st;
     const SysView<T>& s = a.s;
-    const ZPair<T>* __restrict__ zpold = a.zp[P ^ 1];  // {z_{k-1}, p_{k-1}}
-    ZPair<T>* __restrict__ zpnew = a.zp[P];
+    const ZPair<T>* __restrict__ zpold = a.s.zp[P ^ 1];  // {z_{k-1}, p_{k-1}}
+    ZPair<T>* __restrict__ zpnew = a.s.zp[P];
     const int L = logical_of(a.G);
     const bool lead = threadIdx.x == 0 && L == 0;
     T beta = T(0);
@@ -256,7 +250,7 @@ __global__ __launch_bounds__(BS) void k_update(CgArgsT<T> a, int P)
     const double rho = st->rho[P];
     const int L = logical_of(a.G);
     const int rs = min(L * a.R, s.n), re = min(rs + a.R, s.n);
-    ZPair<T>* __restrict__ zp = a.zp[P];  // p_k in .p; z_k goes to .z
+    ZPair<T>* __restrict__ zp = a.s.zp[P];  // p_k in .p; z_k goes to .z
     const int i0 = rs + (int)threadIdx.x;
     const bool h0 = i0 < re;
     const int ic = h0 ? i0 : 0;
@@ -308,7 +302,7 @@ __global__ __launch_bounds__(BS) void k_check(CgArgsT<T> a, int P)
 {
     __shared__ Lds<NPL, BS, T> sh;
     double rr = 0.0, rz = 0.0, bb = 0.0;
-    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.zp[P], rr, rz, bb);
+    tile_residual<NPL, BS, T>(a, sh.prod, a.s.r, a.s.zp[P], rr, rz, bb);
     double v[2] = {rz, rr};
     block_partials<BS, 2>(v, sh.red, a.part_iter[P], logical_of(a.G));
 }
