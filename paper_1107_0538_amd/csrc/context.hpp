@@ -30,11 +30,11 @@ struct cg_ctx {
     std::vector<int> h_rowptr;
 
     // Work vectors for single-RHS solves (one allocation, each vector at a
-    // stride of n rounded up to 64 entries, so every vector and every pair of
-    // vectors starts 512-byte aligned): the standard form uses r, two
-    // interleaved {z, p} pair arrays of two vectors each, and q; the
-    // single-reduction form uses r, w, s (two each) and p.
-    static constexpr int kWorkVecs = 7;
+    // stride of n rounded up to 64 entries, so every vector starts 512-byte
+    // aligned): the standard form uses r, two interleaved {z, p} pair arrays
+    // of two vectors each, and q; the single-reduction form uses two
+    // {r, w, s, d} quad arrays of four vectors each, and p.
+    static constexpr int kWorkVecs = 9;
     double* work[kWorkVecs] = {};
     size_t work_stride = 0;
 

@@ -331,13 +331,9 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
             sa.dinv = c->dinv;
             sa.b = (double*)g->cb;
             sa.x = (double*)g->cx;
-            sa.R[0] = w[0];
-            sa.R[1] = w[1];
-            sa.W[0] = w[2];
-            sa.W[1] = w[3];
-            sa.S[0] = w[4];
-            sa.S[1] = w[5];
-            sa.p = w[6];
+            sa.qd[0] = (SrQuad*)w[0];  // spans w[0..3]
+            sa.qd[1] = (SrQuad*)w[4];  // spans w[4..7]
+            sa.p = w[8];
             sa.tm = tm;
             sa.G = G;
             sa.part[0] = g->part;

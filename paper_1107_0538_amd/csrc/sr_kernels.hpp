@@ -11,8 +11,10 @@
 // gathered u_k(j) on the fly from r_{k-1}, w_{k-1}, s_{k-2} and M^-1 of column
 // j with exactly the expressions the owning row lane uses, so w_k = A u_k
 // for the u_k that the row lanes store implicitly.  The gathered vectors r, w
-// and s alternate between two buffers by iteration parity; p and x update in
-// place (no other row reads them).
+// and s and the Jacobi diagonal are stored together, SrQuad {r, w, s, d} per
+// row, in two arrays used by iteration parity (one 32-byte gather per
+// nonzero; kernels store whole quads where they can); p and x update in place
+// (no other row reads them).
 //
 // After a residual replacement the recurrences behind sigma no longer hold:
 // the restart kernel recomputes s = A p exactly and the partials of u'(A p)
@@ -38,6 +40,10 @@ struct SrState {
     double rr_true;   // ||b - A x||^2 of the returned x
 };
 
+struct alignas(32) SrQuad {
+    double r, w, s, d;
+};
+
 struct SrArgs {
     int n;
     const int* __restrict__ rowptr;
@@ -46,9 +52,7 @@ struct SrArgs {
     const double* __restrict__ dinv;
     const double* b;
     double* x;
-    double* R[2];
-    double* W[2];
-    double* S[2];
+    SrQuad* qd[2];  // by parity: {r, w, s, d} per row
     double* p;
     TileMap tm;
     int G;
@@ -69,15 +73,13 @@ struct SrLds {
 __device__ __forceinline__ int sr_logical(const SrArgs& a) { return xcd_logical_block((int)blockIdx.x, a.G); }
 __device__ __forceinline__ bool sr_leader(const SrArgs& a) { return threadIdx.x == 0 && sr_logical(a) == 0; }
 
-struct Quad {
-    double r, w, s, d;
-};
 struct Six {
-    double r, w, s, d, p, x;
+    SrQuad q;
+    double p, x;
 };
 
-// r0 = b - A x0 into R[0]; clears p and S[0] (read with a zero beta on the
-// first iteration); partials of r'r and b'b.
+// qd[0] = {r0 = b - A x0, 0, 0, d}; clears p (s and p are read with a zero
+// beta on the first iteration); partials of r'r and b'b.
 template <int NPL, int BS>
 __global__ __launch_bounds__(BS) void k_sr_setup(SrArgs a)
 {
@@ -86,12 +88,12 @@ __global__ __launch_bounds__(BS) void k_sr_setup(SrArgs a)
     const double* __restrict__ x = a.x;
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
-        [&](int j) { return x[j]; }, Ident<double>{}, [&](int i) { return a.b[i]; },
-        [&](int i, double ax, double bi) {
+        [&](int j) { return x[j]; }, Ident<double>{}, [&](int i) { return Pair2{a.b[i], a.dinv[i]}; },
+        [&](int i, double ax, Pair2 bd) {
+            const double bi = bd.a;
             const double ri = bi - ax;
-            a.R[0][i] = ri;
+            a.qd[0][i] = SrQuad{ri, 0.0, 0.0, bd.b};
             a.p[i] = 0.0;
-            a.S[0][i] = 0.0;
             v[0] += ri * ri;
             v[1] += bi * bi;
         },
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(BS) void k_sr_setup(SrArgs a)
     block_partials<BS, 2>(v, sh.red, a.part_setup, sr_logical(a));
 }
 
-// Initial tests, then w0 = A u0 into W[0] with the partials of (gamma0,
+// Initial tests, then w0 = A u0 into qd[0].w with the partials of (gamma0,
 // delta0, ||r0||^2) in part[0].
 template <int NPL, int BS>
 __global__ __launch_bounds__(BS) void k_sr_first(SrArgs a, double tol, int maxit)
@@ -136,16 +138,16 @@ __global__ __launch_bounds__(BS) void k_sr_first(SrArgs a, double tol, int maxit
         return;
     }
     if (sqrt(rr) <= thr) return;
-    const double* __restrict__ r0 = a.R[0];
-    const double* __restrict__ dinv = a.dinv;
+    SrQuad* __restrict__ q0 = a.qd[0];
     double v[3] = {0.0, 0.0, 0.0};
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
-        [&](int j) { return Pair2{r0[j], dinv[j]}; }, [&](Pair2 rd) { return rd.b * rd.a; },
-        [&](int i) { return Pair2{r0[i], dinv[i]}; },
+        // Gathers read only the r and d halves; row steps write only w.
+        [&](int j) { return Pair2{q0[j].r, q0[j].d}; }, [&](Pair2 rd) { return rd.b * rd.a; },
+        [&](int i) { return Pair2{q0[i].r, q0[i].d}; },
         [&](int i, double wi, Pair2 rd) {
             const double ui = rd.b * rd.a;
-            a.W[0][i] = wi;
+            q0[i].w = wi;
             v[0] += rd.a * ui;
             v[1] += wi * ui;
             v[2] += rd.a * rd.a;
@@ -161,13 +163,8 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
     __shared__ SrLds<NPL, BS> sh;
     SrState* st = a.st;
     const int Q = P ^ 1;
-    const double* __restrict__ rold = a.R[Q];
-    const double* __restrict__ wold = a.W[Q];
-    const double* __restrict__ sold = a.S[Q];
-    const double* __restrict__ dinv = a.dinv;
-    double* __restrict__ rnew = a.R[P];
-    double* __restrict__ wnew = a.W[P];
-    double* __restrict__ snew = a.S[P];
+    const SrQuad* __restrict__ qold = a.qd[Q];  // {r_{k-1}, w_{k-1}, s_{k-2}, d}
+    SrQuad* __restrict__ qnew = a.qd[P];        // {r_k, w_k, s_{k-1}, d}
     const bool lead = sr_leader(a);
     double alpha = 0.0, beta = 0.0, gam_prev = 0.0;
     int km1 = 0;
@@ -219,23 +216,21 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
     double v[3] = {0.0, 0.0, 0.0};
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
-        [&](int j) { return Quad{rold[j], wold[j], sold[j], dinv[j]}; },
-        [&](Quad q) {
+        [&](int j) { return qold[j]; },
+        [&](SrQuad q) {
             const double s1 = __builtin_fma(beta, q.s, q.w);
             return q.d * __builtin_fma(-alpha, s1, q.r);
         },
-        [&](int i) { return Six{rold[i], wold[i], sold[i], dinv[i], a.p[i], a.x[i]}; },
+        [&](int i) { return Six{qold[i], a.p[i], a.x[i]}; },
         [&](int i, double wi, Six o) {
-            const double u0 = o.d * o.r;
+            const double u0 = o.q.d * o.q.r;
             const double pi = __builtin_fma(beta, o.p, u0);
-            const double si = __builtin_fma(beta, o.s, o.w);
-            const double ri = __builtin_fma(-alpha, si, o.r);
-            const double ui = o.d * ri;
+            const double si = __builtin_fma(beta, o.q.s, o.q.w);
+            const double ri = __builtin_fma(-alpha, si, o.q.r);
+            const double ui = o.q.d * ri;
             a.p[i] = pi;
-            snew[i] = si;
             a.x[i] = __builtin_fma(alpha, pi, o.x);
-            rnew[i] = ri;
-            wnew[i] = wi;
+            qnew[i] = SrQuad{ri, wi, si, o.q.d};
             v[0] += ri * ui;
             v[1] += wi * ui;
             v[2] += ri * ri;
@@ -251,20 +246,20 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
     }
 }
 
-// ||b - A x||^2 into part_chk; if rout, the true residual replaces R[P] there.
+// ||b - A x||^2 into part_chk; with replace, the true residual replaces qd[P].r.
 template <int NPL, int BS>
 __global__ __launch_bounds__(BS) void k_sr_residual(SrArgs a, int P, int replace)
 {
     __shared__ SrLds<NPL, BS> sh;
     double v[1] = {0.0};
     const double* __restrict__ x = a.x;
-    double* __restrict__ rout = a.R[P];
+    SrQuad* __restrict__ qout = a.qd[P];
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
         [&](int j) { return x[j]; }, Ident<double>{}, [&](int i) { return a.b[i]; },
         [&](int i, double ax, double bi) {
             const double ri = bi - ax;
-            if (replace) rout[i] = ri;
+            if (replace) qout[i].r = ri;
             v[0] += ri * ri;
         },
         NoPrologue{});
@@ -292,36 +287,37 @@ __global__ __launch_bounds__(BS) void k_sr_decide(SrArgs a, int report)
     }
 }
 
-// After a replacement: w = A M^-1 r for the replaced r in R[P], with the
+// After a replacement: w = A M^-1 r for the replaced r in qd[P], with the
 // partials of (gamma, delta, r'r) in part[P] for the next iteration; then
-// s = A p into S[P] with the partials of u'(A p) and p'(A p) in part_rst.
+// s = A p into qd[P].s with the partials of u'(A p) and p'(A p) in part_rst.
 template <int NPL, int BS>
 __global__ __launch_bounds__(BS) void k_sr_restart(SrArgs a, int P)
 {
     __shared__ SrLds<NPL, BS> sh;
-    const double* __restrict__ r = a.R[P];
-    const double* __restrict__ dinv = a.dinv;
+    SrQuad* __restrict__ q = a.qd[P];
     const double* __restrict__ p = a.p;
     double* prod = sh.prod + (threadIdx.x / kWave) * (kWave * NPL);
     double v[3] = {0.0, 0.0, 0.0};
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), prod,
-        [&](int j) { return Pair2{r[j], dinv[j]}; }, [&](Pair2 rd) { return rd.b * rd.a; },
-        [&](int i) { return Pair2{r[i], dinv[i]}; },
+        [&](int j) { return Pair2{q[j].r, q[j].d}; }, [&](Pair2 rd) { return rd.b * rd.a; },
+        [&](int i) { return Pair2{q[i].r, q[i].d}; },
         [&](int i, double wi, Pair2 rd) {
             const double ui = rd.b * rd.a;
-            a.W[P][i] = wi;
+            q[i].w = wi;
             v[0] += rd.a * ui;
             v[1] += wi * ui;
             v[2] += rd.a * rd.a;
         },
         NoPrologue{});
+    // The second product's gathers read only p, and its row steps write only
+    // the s half of the quads, so the first product's w stores cannot race.
     double e[2] = {0.0, 0.0};
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), prod, [&](int j) { return p[j]; }, Ident<double>{},
-        [&](int i) { return Pair2{p[i], dinv[i] * r[i]}; },
+        [&](int i) { return Pair2{p[i], q[i].d * q[i].r}; },
         [&](int i, double si, Pair2 pu) {
-            a.S[P][i] = si;
+            q[i].s = si;
             e[0] += pu.b * si;
             e[1] += pu.a * si;
         },
