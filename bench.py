@@ -56,8 +56,8 @@ def solve_bytes(n, nnz, iters, checks, form="standard", vb=8, ib=4):
 # 512 MiB copy: fetch x2, write x1) for the 51^3 system, keyed by form and
 # launch shape (nonzeros per lane, block size, column index bits).
 MEASURED_TRAFFIC = {
-    ("standard", 132651, 3442951, 16, 512, 16): 51.94e6,  # k_direction + k_update
-    ("single", 132651, 3442951, 8, 512, 16): 49.29e6,     # k_sr_iter
+    ("standard", 132651, 3442951, 16, 512, 16): 51.95e6,  # k_direction + k_update
+    ("single", 132651, 3442951, 8, 512, 16): 50.00e6,     # k_sr_iter
 }
 
 
@@ -75,8 +75,9 @@ def roofline(form, n, nnz, run):
     traffic = MEASURED_TRAFFIC.get((form, n, nnz, launch["nnz_per_lane"], launch["block_size"], launch["col_bits"]))
     # The stored format's compulsory bytes: 16-bit column offsets save 2 per
     # nonzero against the CSR count that `achieved` uses; the standard form's
-    # whole {z, p} pair stores and loads add 24 per row.
-    fb = ib - (2 * nnz if launch.get("col_bits") == 16 else 0) + (24 * n if form == "standard" else 0)
+    # whole {z, p} pair stores and loads add 24 per row, the single-reduction
+    # form's whole {r, w, s, d} quad stores 8.
+    fb = ib - (2 * nnz if launch.get("col_bits") == 16 else 0) + (24 * n if form == "standard" else 8 * n)
     return {
         "kernel": ("k_sr_iter" if form == "single" else "k_direction + k_update") + " (one CG iteration)",
         "bound": "hbm", "achieved": ib / per_iter_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
