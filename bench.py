@@ -57,7 +57,7 @@ def solve_bytes(n, nnz, iters, checks, form="standard", vb=8, ib=4):
 # launch shape (nonzeros per lane, block size, column index bits).
 MEASURED_TRAFFIC = {
     ("standard", 132651, 3442951, 16, 512, 16): 51.95e6,  # k_direction + k_update
-    ("single", 132651, 3442951, 8, 512, 16): 50.00e6,     # k_sr_iter
+    ("single", 132651, 3442951, 16, 512, 16): 49.60e6,    # k_sr_iter
 }
 
 

@@ -76,8 +76,7 @@ typedef struct {
     int32_t autotune;      /* 1: time launch shapes at create and keep the fastest       */
                            /* (cg_create: reused for later matrices of the same size    */
                            /* and row profile; cg_batch_create: the tile width)         */
-    int32_t nnz_per_lane;  /* 4, 8 or 16: a product tile holds 64x that; 0 = default  */
-                           /* (16, or 8 for the single-reduction form)                 */
+    int32_t nnz_per_lane;  /* 4, 8 or 16: a product tile holds 64x that; 0 = 16       */
     int32_t blocks_per_cu; /* 0 = default; workgroups per compute unit of the grid      */
     int32_t history;       /* 1: record ||r_k|| / ||b|| for every iteration            */
     int32_t block_size;    /* 0 = default; else 256, 512 or 1024 threads per workgroup  */

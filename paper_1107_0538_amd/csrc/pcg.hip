@@ -891,11 +891,10 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
         // Launch shape: defaults, explicit options, or the autotuner.
         c->chunk = c->opts.chunk ? c->opts.chunk : 16;
         c->form = c->opts.form;
-        // Default tile width: the fastest measured at the paper's size (fewer,
-        // fuller tiles amortise each tile's load-gather-sum latency chain);
-        // the single-reduction kernel holds four gathered vectors and would
-        // spill at 16.
-        c->npl = c->opts.nnz_per_lane ? c->opts.nnz_per_lane : (c->form == CG_FORM_SINGLE_REDUCTION ? 8 : 16);
+        // Default tile width: the fastest measured at the paper's size and at
+        // 128^3 in both forms (fewer, fuller tiles amortise each tile's
+        // load-gather-sum latency chain).
+        c->npl = c->opts.nnz_per_lane ? c->opts.nnz_per_lane : 16;
         c->bs = c->opts.block_size ? c->opts.block_size : 512;
         if (c->npl == 16 && c->bs == 1024) c->bs = 512;  // product tiles must fit 64 KiB of LDS
         c->grid = default_grid(c, c->npl, c->bs, c->opts.blocks_per_cu ? c->opts.blocks_per_cu : 1);
