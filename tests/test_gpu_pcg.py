@@ -6,6 +6,8 @@ ill-posed); solves within +-2 iterations, solution relative error <= 1e-8 and
 true relative residual <= 1e-10, recomputed on the CPU in FP64.
 """
 import functools
+import json
+import os
 
 import numpy as np
 import pytest
@@ -423,3 +425,33 @@ def test_column_offset_limit(cuda, link, bits, npl):
     xo, io = oracle.pcg(a, b)
     assert info["status"] == io["status"] == 0 and abs(info["iters"] - io["iters"]) <= 2
     assert np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_solve_max_size_against_stored_oracle(cuda, form):
+    # 128^3 (N = 2,097,152, nnz = 55,742,968) in the default launch shape
+    # against the oracle's solves stored by tests/golden/make_q1hex128.py
+    # (minutes of CPU per solve): same ending, iterations within +-2, and the
+    # solution on 1024 sampled rows.  The single-reduction form ends in
+    # BREAKDOWN near the attainable accuracy at this size, like its oracle.
+    from paper_1107_0538_amd import Solver
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "q1hex128_oracle.json")
+    with open(path) as f:
+        g = json.load(f)
+    a, b = prob(128)
+    assert (a.n, int(a.rowptr[-1])) == (g["n"], g["nnz"])
+    go = g["forms"][form]
+    s = Solver(a, form=form)
+    x, info = s.solve(_t(b, cuda))
+    xg = x.cpu().numpy()
+    assert info["status"] == go["status"]
+    assert abs(info["iters"] - go["iters"]) <= 2, (info, go)
+    rr = oracle.relres(a, b, xg)
+    if go["status"] == 0:
+        assert rr <= TOL_RECOMPUTED
+        ref = np.array(go["x_rows"])
+        assert np.linalg.norm(xg[g["rows"]] - ref) / np.linalg.norm(ref) <= 1e-8
+        assert abs(np.linalg.norm(xg) - go["x_norm"]) <= 1e-8 * go["x_norm"]
+    else:
+        assert rr <= 10 * go["relres_true"]

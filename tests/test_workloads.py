@@ -115,3 +115,19 @@ def test_batch_sizes_in_range():
     sys = W.batch_systems(count=3)
     for n, a, b in sys:
         assert 12 <= n <= 48 and a.n == n ** 3 and a.nnz == (3 * n - 2) ** 3 and b.shape == (a.n,)
+
+
+def test_stored_oracle_values_128():
+    # The stored 128^3 oracle solves (tests/golden/make_q1hex128.py) describe
+    # this workload: sizes by the closed forms, the standard form converged.
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "q1hex128_oracle.json")) as f:
+        g = json.load(f)
+    assert g["n"] == 128 ** 3 and g["nnz"] == (3 * 128 - 2) ** 3
+    rows = g["rows"]
+    assert len(rows) == len(set(rows)) == 1024 and rows == sorted(rows) and 0 <= rows[0] and rows[-1] < g["n"]
+    st = g["forms"]["standard"]
+    assert st["status"] == 0 and st["relres_true"] <= 1e-10 and 0 < st["iters"] <= g["n"]
+    assert len(st["x_rows"]) == 1024 and st["x_norm"] > 0
