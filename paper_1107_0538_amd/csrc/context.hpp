@@ -8,8 +8,9 @@
 #include "phases.hpp"
 
 namespace jpcg {
-// Zero entries after the last nonzero of the context's col and val arrays.
-constexpr int kCsrPad = 16;
+// Zero entries after the last nonzero of the context's col and val arrays
+// (the multi-RHS row products read batches of up to 32 past a row's start).
+constexpr int kCsrPad = 32;
 }  // namespace jpcg
 
 struct cg_ctx {

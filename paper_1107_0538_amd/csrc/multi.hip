@@ -86,6 +86,7 @@ struct MrArgs {
 
 __device__ __forceinline__ int mr_logical(int G) { return xcd_logical_block((int)blockIdx.x, G); }
 
+
 // Block-reduce K per-lane quantities over the waves (lane = column) and write
 // them to part[L][k][lane].
 template <int BS, int K>
@@ -108,6 +109,11 @@ __device__ __forceinline__ void mr_block_partials(double (&v)[K], double* part, 
     }
 }
 
+// Nonzeros of a row whose gathers a wave issues together: 16 with one
+// column per lane, 32 (16 per half-wave) with two (mr_row_x2).
+constexpr int kMrBatch = 16;
+constexpr int kMrBatch2 = 32;
+
 // One wave: y_lane = sum_k a_ik x[col_k][lane] for row i in stored order,
 // without contraction, so each column is the sequential CSR row sum.
 template <typename T, typename Gather>
@@ -115,12 +121,12 @@ __device__ __forceinline__ T mr_row(const int* __restrict__ rowptr, const int* _
                                     const T* __restrict__ val, int i, Gather gather)
 {
 #pragma clang fp contract(off)
-    // Batches of 16 nonzeros: the (wave-uniform) indices and values are
-    // loaded, then all 16 gathers are in flight together; the tail batch
-    // reads past the row's end (into the next row or the arrays' zero pad of
-    // kCsrPad entries) and skips those slots, so a 27-entry row takes two
-    // gather round trips.
-    constexpr int B = 16;
+    // Batches of kMrBatch nonzeros: the (wave-uniform) indices and values
+    // are loaded, then all the batch's gathers are in flight together; the
+    // tail batch reads past the row's end (into the next row or the arrays'
+    // zero pad of kCsrPad entries) and skips those slots, so a 27-entry row
+    // takes two gather round trips.
+    constexpr int B = kMrBatch;
     static_assert(B <= kCsrPad, "batch reads must stay within the padded arrays");
     // The row is the same in every lane: make that explicit so that the
     // row's indices and values come through the scalar cache.
@@ -141,6 +147,54 @@ __device__ __forceinline__ T mr_row(const int* __restrict__ rowptr, const int* _
     return acc;
 }
 
+// The same row product with two nonzeros per gather instruction (FP64, s
+// even): lane l takes columns 2 (l mod 32) and 2 (l mod 32) + 1 of the
+// nonzeros at even (lower half) or odd (upper half) positions of each batch,
+// so one 16-byte load per lane fetches two nonzeros' rows of X.  This
+// gather-heavy product is limited by the per-CU address path, which handles a
+// 16-byte lane as fast as an 8-byte one, not by bytes.  Products are rounded
+// on their own; the upper half hands its products to the lower half, which
+// adds them in stored order, so both columns are the sequential CSR row sums
+// bitwise (as mr_row).  The sums are valid in the lower half's lanes.
+template <typename Gather2>
+__device__ __forceinline__ double2 mr_row_x2(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                             const double* __restrict__ val, int i, Gather2 gather2)
+{
+#pragma clang fp contract(off)
+    constexpr int B = kMrBatch2;  // nonzeros per batch, half of them per half-wave
+    static_assert(B <= kCsrPad, "batch reads must stay within the padded arrays");
+    i = __builtin_amdgcn_readfirstlane(i);
+    const int k0 = __builtin_amdgcn_readfirstlane(rowptr[i]), k1 = __builtin_amdgcn_readfirstlane(rowptr[i + 1]);
+    const bool upper = (threadIdx.x & 32) != 0;
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = k0; k < k1; k += B) {
+        double v[B / 2];
+        double2 g[B / 2];
+#pragma unroll
+        for (int u = 0; u < B / 2; ++u) {
+            const int ke = k + 2 * u;
+            const double ve = val[ke], vo = val[ke + 1];
+            const int ce = col[ke], co = col[ke + 1];
+            v[u] = upper ? vo : ve;
+            g[u] = gather2(upper ? co : ce);
+        }
+#pragma unroll
+        for (int u = 0; u < B / 2; ++u) {
+            const double p0 = v[u] * g[u].x, p1 = v[u] * g[u].y;
+            const double q0 = __shfl_xor(p0, 32), q1 = __shfl_xor(p1, 32);  // the other half's products
+            if (k + 2 * u < k1) {
+                a0 = a0 + p0;
+                a1 = a1 + p1;
+            }
+            if (k + 2 * u + 1 < k1) {
+                a0 = a0 + q0;
+                a1 = a1 + q1;
+            }
+        }
+    }
+    return make_double2(a0, a1);
+}
+
 // True in every thread if some column is active (each wave reads the 64
 // statuses once).
 __device__ __forceinline__ bool mr_any_active(const MrState* st)
@@ -157,7 +211,7 @@ __device__ __forceinline__ T mr_row_diff(const int* __restrict__ rowptr, const i
                                          const T* __restrict__ val, const T* __restrict__ rowsum, int i, T xi,
                                          Gather gather)
 {
-    constexpr int B = 16;
+    constexpr int B = kMrBatch;
     static_assert(B <= kCsrPad, "batch reads must stay within the padded arrays");
     i = __builtin_amdgcn_readfirstlane(i);
     const int k0 = __builtin_amdgcn_readfirstlane(rowptr[i]), k1 = __builtin_amdgcn_readfirstlane(rowptr[i + 1]);
@@ -255,6 +309,32 @@ __global__ __launch_bounds__(BS) void k_mr_direction(MrArgs<T> a, int P)
     const bool active = used && st->status[lane] == COL_ACTIVE;
     const T* __restrict__ pnew = a.P[P];
     double v[1] = {0.0};
+    if constexpr (sizeof(T) == 8) {
+        if (s % 2 == 0) {  // two nonzeros per gather; lane = column pair in the lower half
+            const int c2 = 2 * (lane & 31);
+            const bool pair = lane < 32 && c2 < s;
+            const int cp = c2 < s ? c2 : 0;
+            const bool act0 = pair && st->status[cp] == COL_ACTIVE, act1 = pair && st->status[cp + 1] == COL_ACTIVE;
+            double v0 = 0.0, v1 = 0.0;
+            for (int i = rs + w; i < re; i += BS / kWave) {
+                const size_t o = (size_t)i * s + cp;
+                const double2 qi = mr_row_x2(a.rowptr, a.col, a.val, i, [&](int j) {
+                    return *(const double2*)(pnew + (size_t)j * s + cp);
+                });
+                if (pair) {
+                    *(double2*)(a.Q + o) = qi;
+                    const double2 pi = *(const double2*)(pnew + o);
+                    if (act0) v0 += pi.x * qi.x;
+                    if (act1) v1 += pi.y * qi.y;
+                }
+            }
+            // Back to lane = column for the block partials.
+            const double w0 = __shfl(v0, lane >> 1), w1 = __shfl(v1, lane >> 1);
+            v[0] = (lane & 1) ? w1 : w0;
+            mr_block_partials<BS, 1>(v, a.part, L);
+            return;
+        }
+    }
     for (int i = rs + w; i < re; i += BS / kWave) {
         const size_t o = (size_t)i * s + cl;
         auto gather = [&](int j) { return pnew[(size_t)j * s + cl]; };
@@ -457,6 +537,20 @@ __global__ __launch_bounds__(BS) void k_spmm(int n, int s, const int* __restrict
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int rs = min(L * rows_per_block, n), re = min(rs + rows_per_block, n);
     const int cl = lane < s ? lane : 0;
+    if constexpr (sizeof(T) == 8) {
+        if (s % 2 == 0) {  // two nonzeros per gather (see mr_row_x2)
+            const int c2 = 2 * (lane & 31);
+            const bool pair = lane < 32 && c2 < s;
+            const int cp = c2 < s ? c2 : 0;
+            for (int i = rs + w; i < re; i += BS / kWave) {
+                const double2 y = mr_row_x2(rowptr, col, val, i, [&](int j) {
+                    return *(const double2*)(X + (size_t)j * s + cp);
+                });
+                if (pair) *(double2*)(Y + (size_t)i * s + cp) = y;
+            }
+            return;
+        }
+    }
     for (int i = rs + w; i < re; i += BS / kWave) {
         const T y = mr_row<T>(rowptr, col, val, i, [&](int j) { return X[(size_t)j * s + cl]; });
         if (lane < s) Y[(size_t)i * s + lane] = y;
