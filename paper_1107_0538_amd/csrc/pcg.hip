@@ -235,7 +235,10 @@ struct cg_graphs {
     void* cb = nullptr;      // the solver's own b and x: graphs bind fixed addresses
     void* cx = nullptr;
     void* work32 = nullptr;  // FP32 work vectors: r, two {z, p} pair arrays, q (6 strides)
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    // exec[P][q]: a chunk whose first iteration has parity P, ending with the
+    // copy of the state block into pinned slot q (the host reads slot q after
+    // the chunk's event; four slots so that two chunks can be in flight).
+    hipGraphExec_t exec[2][4] = {};
     hipEvent_t evs[4] = {nullptr, nullptr, nullptr, nullptr};
     jpcg::CgArgsT<double> args{};
     jpcg::CgArgsT<float> args32{};
@@ -247,8 +250,9 @@ namespace jpcg {
 static void destroy_graphs(cg_graphs* g)
 {
     if (!g) return;
-    for (auto& e : g->exec)
-        if (e) (void)hipGraphExecDestroy(e);
+    for (auto& row : g->exec)
+        for (auto& e : row)
+            if (e) (void)hipGraphExecDestroy(e);
     for (auto& e : g->evs)
         if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {g->tiles, g->col16, g->part, g->st, g->cb, g->cx, g->work32};
@@ -347,7 +351,8 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
         JPCG_HIP(hipStreamSynchronize(c->stream));
         hipStream_t cap;
         JPCG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        for (int par = 0; par < 2; ++par) {
+        for (int pq = 0; pq < 8; ++pq) {
+            const int par = pq >> 2, q = pq & 3;
             hipGraph_t graph;
             JPCG_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
             for (int it = 0; it < chunk; ++it) {
@@ -361,8 +366,9 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
                     launch(g->kern.update, G, bs, cap, args);
                 }
             }
+            JPCG_HIP(hipMemcpyAsync((char*)g->hst + q * g->st_bytes, g->st, g->st_bytes, hipMemcpyDeviceToHost, cap));
             JPCG_HIP(hipStreamEndCapture(cap, &graph));
-            hipError_t e = hipGraphInstantiate(&g->exec[par], graph, nullptr, nullptr, 0);
+            hipError_t e = hipGraphInstantiate(&g->exec[par][q], graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             JPCG_HIP(e);
         }
@@ -397,11 +403,11 @@ static void chunk_loop(cg_ctx* c, cg_graphs* g, int first_k, int maxit, bool use
     char* hst = (char*)g->hst;
     while (true) {
         if (use_graph) {
-            JPCG_HIP(hipGraphLaunch(g->exec[next_k & 1], s));
+            JPCG_HIP(hipGraphLaunch(g->exec[next_k & 1][slot], s));  // copies the state into slot
         } else {
             for (int it = 0; it < g->chunk; ++it) iteration((next_k + it) & 1);
+            JPCG_HIP(hipMemcpyAsync(hst + slot * g->st_bytes, g->st, g->st_bytes, hipMemcpyDeviceToHost, s));
         }
-        JPCG_HIP(hipMemcpyAsync(hst + slot * g->st_bytes, g->st, g->st_bytes, hipMemcpyDeviceToHost, s));
         JPCG_HIP(hipEventRecord(g->evs[slot], s));
         next_k += g->chunk;
         launched += g->chunk;
