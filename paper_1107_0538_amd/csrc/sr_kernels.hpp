@@ -169,13 +169,24 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
     double alpha = 0.0, beta = 0.0, gam_prev = 0.0;
     int km1 = 0;
     bool go = false;
+    __shared__ double s_g[3];
     auto prologue = [&]() -> bool {
         const int stop = st->stop, maxit = st->maxit, rst = st->rst[Q];
         km1 = st->kk[Q];
         const double thr = st->thr, nb = st->nb, gam2 = st->gam[Q], alpha1 = st->alpha[Q];
-        double g[3];
-        wave_grid_sum<3>(a.part[Q], a.G, g);
-        const double gam = g[0], delta = g[1], rr = g[2];
+        // Wave 0 reduces the partials for the workgroup (every wave calls the
+        // prologue exactly once, so the barrier is met by all of them).
+        if (threadIdx.x < kWave) {
+            double g0[3];
+            wave_grid_sum<3>(a.part[Q], a.G, g0);
+            if (threadIdx.x == 0) {
+                s_g[0] = g0[0];
+                s_g[1] = g0[1];
+                s_g[2] = g0[2];
+            }
+        }
+        __syncthreads();
+        const double gam = s_g[0], delta = s_g[1], rr = s_g[2];
         if (stop != RUNNING) return false;
         if (lead) {
             st->rr = rr;

@@ -188,12 +188,22 @@ __global__ __launch_bounds__(BS) void k_direction(CgArgsT<T> a, int P)
     T beta = T(0);
     double sig = 0.0;
     bool go = true;
+    __shared__ double s_g[2];
     auto prologue = [&]() -> bool {
         const int stop = st->stop, km1 = st->k, maxit = st->maxit;
         const double thr = st->thr, nb = st->nb, rho_prev = st->rho[P ^ 1];
-        double g[2];
-        wave_grid_sum<2>(a.part_iter[P ^ 1], a.G, g);
-        const double rz = g[0], rr = g[1];
+        // Wave 0 reduces the partials for the workgroup and shares them
+        // through LDS (every wave calls the prologue exactly once).
+        if (threadIdx.x < kWave) {
+            double g[2];
+            wave_grid_sum<2>(a.part_iter[P ^ 1], a.G, g);
+            if (threadIdx.x == 0) {
+                s_g[0] = g[0];
+                s_g[1] = g[1];
+            }
+        }
+        __syncthreads();
+        const double rz = s_g[0], rr = s_g[1];
         go = false;
         if (stop != RUNNING) return false;
         if (lead) {
@@ -256,9 +266,15 @@ __global__ __launch_bounds__(BS) void k_update(CgArgsT<T> a, int P)
     const int ic = h0 ? i0 : 0;
     const T p0 = zp[ic].p, q0 = s.q[ic], x0 = s.x[ic], r0 = s.r[ic], d0 = s.dinv[ic];
     // z_k is written with p_k as a whole pair (full 2-element stores).
-    double g[1];
-    wave_grid_sum<1>(a.part_sig, a.G, g);
-    const double sigma = g[0];
+    // Wave 0 reduces the partials of sigma for the workgroup.
+    if (threadIdx.x < kWave) {
+        double g[1];
+        wave_grid_sum<1>(a.part_sig, a.G, g);
+        if (threadIdx.x == 0) sh.red[0] = g[0];
+    }
+    __syncthreads();
+    const double sigma = sh.red[0];
+    __syncthreads();  // sh.red is reused by block_partials below
     if (stop != RUNNING) return;
     const bool lead = threadIdx.x == 0 && L == 0;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
