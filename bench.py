@@ -56,8 +56,8 @@ def solve_bytes(n, nnz, iters, checks, form="standard", vb=8, ib=4):
 # 512 MiB copy: fetch x2, write x1) for the 51^3 system, keyed by form and
 # launch shape (nonzeros per lane, block size, column index bits).
 MEASURED_TRAFFIC = {
-    ("standard", 132651, 3442951, 16, 512, 16): 51.95e6,  # k_direction + k_update
-    ("single", 132651, 3442951, 16, 512, 16): 49.60e6,    # k_sr_iter
+    ("standard", 132651, 3442951, 16, 512, 16): 51.94e6,  # k_direction + k_update
+    ("single", 132651, 3442951, 16, 512, 16): 49.51e6,    # k_sr_iter
 }
 
 
