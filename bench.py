@@ -57,7 +57,7 @@ def solve_bytes(n, nnz, iters, checks, form="standard", vb=8, ib=4):
 # launch shape (nonzeros per lane, block size, column index bits).
 MEASURED_TRAFFIC = {
     ("standard", 132651, 3442951, 16, 512, 16): 51.94e6,  # k_direction + k_update
-    ("single", 132651, 3442951, 16, 512, 16): 49.51e6,    # k_sr_iter
+    ("single", 132651, 3442951, 16, 512, 16): 49.52e6,    # k_sr_iter
 }
 
 
@@ -473,7 +473,9 @@ def main():
         "spmv": {
             "us": spmv_us, "gbs": sb / spmv_us / 1e3, "frac_hbm_peak": sb / spmv_us / 1e3 / HBM_PEAK_GBS,
             "cold_us_median": statistics.median(cold), "cold_gbs": sb / statistics.median(cold) / 1e3,
-            "bytes": sb, "nnz_per_lane": cfg["nnz_per_lane"],
+            "bytes": sb, "format_bytes": sb - (2 * nnz if cfg["col_bits"] == 16 else 0),
+            "kernel": f"k_spmv<{cfg['spmv_nnz_per_lane']}, {cfg['spmv_block_size']}>",
+            "nnz_per_lane": cfg["spmv_nnz_per_lane"], "block_size": cfg["spmv_block_size"], "grid": cfg["spmv_grid"],
         },
         "roofline": roofline(best, n, nnz, r),
         "paper_context": {"opencl_1gpu_tesla_t10_s": 0.659, "matlab_core2duo_s": 3.17,

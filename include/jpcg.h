@@ -104,7 +104,7 @@ typedef struct {
 typedef struct {
     int32_t nnz_per_lane;  /* a product tile holds up to 64 * nnz_per_lane nonzeros */
     int32_t block_size;
-    int32_t grid;          /* workgroups of every solver kernel and of spmv       */
+    int32_t grid;          /* workgroups of every solver kernel                   */
     int32_t tiles;         /* product tiles (runs of whole rows) of the matrix    */
     int32_t chunk;         /* iterations per hipGraph chunk                       */
     int32_t form;          /* CG_FORM_STANDARD or CG_FORM_SINGLE_REDUCTION        */
@@ -112,6 +112,10 @@ typedef struct {
                               this process for a matrix of the same size and
                               row-length profile (no timing at this create)     */
     int32_t col_bits;      /* 16 or 32: column index width the products read      */
+    int32_t spmv_nnz_per_lane; /* spmv's own tiling, block size and grid: the       */
+    int32_t spmv_block_size;   /* solver's shape if opts gave one, else tile width */
+    int32_t spmv_grid;         /* 8, block 512, two workgroups per CU (autotuned   */
+                               /* separately when opts->autotune is set)           */
     double spmv_us;        /* autotuner's best spmv time, 0 if not tuned          */
     double iter_us;        /* autotuner's best solver time per iteration, or 0    */
 } cg_config;
@@ -168,7 +172,9 @@ int cg_solve_mixed(cg_ctx *ctx, const double *b, double *x, double tol, int32_t 
                    double tol_inner, int32_t maxit_inner, cg_info *info);
 
 /* y = A x (the paper's "DGEMV(sparse)").  Device pointers to float64[n], x != y.
- * Asynchronous on the context's stream.  Returns 0 or an API error. */
+ * Rows are summed in stored order (bitwise the sequential CSR product), with
+ * the product's own tiling and grid (cg_config.spmv_*).  Asynchronous on the
+ * context's stream.  Returns 0 or an API error. */
 int spmv(cg_ctx *ctx, const double *x, double *y);
 
 /*

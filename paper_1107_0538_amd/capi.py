@@ -47,7 +47,9 @@ class cg_info(ctypes.Structure):
 class cg_config(ctypes.Structure):
     _fields_ = [("nnz_per_lane", ctypes.c_int32), ("block_size", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("tiles", ctypes.c_int32), ("chunk", ctypes.c_int32), ("form", ctypes.c_int32),
-                ("tune_cached", ctypes.c_int32), ("col_bits", ctypes.c_int32), ("spmv_us", ctypes.c_double), ("iter_us", ctypes.c_double)]
+                ("tune_cached", ctypes.c_int32), ("col_bits", ctypes.c_int32),
+                ("spmv_nnz_per_lane", ctypes.c_int32), ("spmv_block_size", ctypes.c_int32),
+                ("spmv_grid", ctypes.c_int32), ("spmv_us", ctypes.c_double), ("iter_us", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -45,6 +45,7 @@ struct cg_ctx {
     struct cg_graphs* graphs32 = nullptr;    // standard form FP32 (mixed-form inner solve)
     void* mixed_dev = nullptr;
     void* mixed_host = nullptr;
+    struct cg_spmv_plan* spmv = nullptr;     // the standalone product's tiling and grid
     struct cg_multi* multi = nullptr;        // multi-RHS solver for one block width
     struct cg_multi* multi32 = nullptr;      // FP32 multi-RHS inner solver (mixed form)
     double* hist = nullptr;

@@ -380,11 +380,68 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
     }
 }
 
+}  // namespace jpcg
+
+// The standalone product (spmv) has its own tiling and grid: it carries no
+// partial sums, so its grid is not tied to the solver's, and the product
+// alone runs best with more, smaller tiles in flight (tile width 8, two
+// workgroups of 512 per CU at 51^3) than the solver kernels, whose reduction
+// of the previous kernel's partials grows with the grid.
+struct cg_spmv_plan {
+    int npl = 0, bs = 0, G = 0, T = 0;
+    int4* tiles = nullptr;
+    unsigned short* col16 = nullptr;
+    const void* kern = nullptr;
+    jpcg::CgArgsT<double> args{};
+};
+
+namespace jpcg {
+
+static void destroy_spmv_plan(cg_spmv_plan* p)
+{
+    if (!p) return;
+    if (p->tiles) (void)hipFree(p->tiles);
+    if (p->col16) (void)hipFree(p->col16);
+    delete p;
+}
+
+static cg_spmv_plan* make_spmv_plan(cg_ctx* c, int npl, int bs, int G)
+{
+    cg_spmv_plan* p = new cg_spmv_plan();
+    try {
+        CgKernels k{};
+        if (!kernels_t<double>(npl, bs, k)) throw HipError{hipErrorInvalidValue, "launch shape"};
+        p->npl = npl;
+        p->bs = bs;
+        p->G = G;
+        p->kern = k.spmv;
+        std::vector<int4> tiles;
+        build_tiles(c->h_rowptr, kWave * npl, tiles);
+        p->T = (int)tiles.size();
+        JPCG_HIP(hipMalloc(&p->tiles, sizeof(int4) * std::max(p->T, 1)));
+        if (p->T)
+            JPCG_HIP(hipMemcpyAsync(p->tiles, tiles.data(), sizeof(int4) * p->T, hipMemcpyHostToDevice, c->stream));
+        if (c->opts.col_bits != 32) p->col16 = make_col16(c->stream, p->tiles, p->T, c->col, c->nnz);
+        JPCG_HIP(hipStreamSynchronize(c->stream));
+        CgArgsT<double>& a = p->args;
+        a.s = SysView<double>{c->n, c->rowptr, c->col, c->val, c->dinv, nullptr, nullptr, nullptr,
+                              {nullptr, nullptr}, nullptr};
+        a.rowsum = nullptr;
+        a.tm = TileMap{p->tiles, p->T, (p->T + G - 1) / G, p->col16};
+        a.R = (c->n + G - 1) / G;
+        a.G = G;
+        return p;
+    } catch (...) {
+        destroy_spmv_plan(p);
+        throw;
+    }
+}
+
 static void launch_spmv(cg_ctx* c, const double* x, double* y)
 {
-    cg_graphs* g = c->graphs;
-    void* args[] = {&g->args, &x, &y};
-    launch(g->kern.spmv, g->G, g->bs, c->stream, args);
+    cg_spmv_plan* p = c->spmv;
+    void* args[] = {&p->args, &x, &y};
+    launch(p->kern, p->G, p->bs, c->stream, args);
 }
 
 // The chunk loop shared by both forms: two chunks in flight; the state block
@@ -652,6 +709,7 @@ struct TuneKey {
 struct TuneResult {
     int npl, bs, G;
     double iter_us, spmv_us;
+    int spmv_npl, spmv_bs, spmv_G;
 };
 static std::mutex g_tune_mutex;
 static std::map<TuneKey, TuneResult> g_tune_cache;
@@ -679,6 +737,7 @@ static void autotune(cg_ctx* c)
             c->grid = r.G;
             c->tuned_iter_us = r.iter_us;
             c->tuned_spmv_us = r.spmv_us;
+            c->spmv = make_spmv_plan(c, r.spmv_npl, r.spmv_bs, r.spmv_G);
             c->tune_cached = true;
             return;
         }
@@ -732,21 +791,50 @@ static void autotune(cg_ctx* c)
     c->npl = keep->npl;
     c->bs = keep->bs;
     c->grid = keep->G;
-    // Standalone product with the chosen shape.
+    // The standalone product's own shape: time each tiling and grid.
     const int reps = 20;
-    launch_spmv(c, yb, xb);
-    JPCG_HIP(hipEventRecord(e0, c->stream));
-    for (int r = 0; r < reps; ++r) launch_spmv(c, yb, xb);
-    JPCG_HIP(hipEventRecord(e1, c->stream));
-    JPCG_HIP(hipEventSynchronize(e1));
-    JPCG_HIP(hipEventElapsedTime(&ms, e0, e1));
-    c->tuned_spmv_us = ms * 1e3 / reps;
+    float best_spmv = 1e30f;
+    const int pshapes[][2] = {{4, 512}, {8, 256}, {8, 512}, {16, 256}, {16, 512}};
+    for (const auto& sh : pshapes) {
+        for (int bpc : {1, 2, 4}) {
+            // The candidate is made current for timing; afterwards the better
+            // of it and the best so far stays in c->spmv, the other is freed.
+            cg_spmv_plan* p = nullptr;
+            bool current = false;
+            try {
+                p = make_spmv_plan(c, sh[0], sh[1], default_grid(c, sh[0], sh[1], bpc));
+                std::swap(p, c->spmv);  // p: the best so far (or none)
+                current = true;
+                launch_spmv(c, yb, xb);
+                JPCG_HIP(hipEventRecord(e0, c->stream));
+                for (int r = 0; r < reps; ++r) launch_spmv(c, yb, xb);
+                JPCG_HIP(hipEventRecord(e1, c->stream));
+                JPCG_HIP(hipEventSynchronize(e1));
+                JPCG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            } catch (const HipError&) {
+                (void)hipGetLastError();  // a shape this device cannot launch
+                ms = 1e30f;
+            }
+            if (!current) continue;  // the candidate was never made
+            if (ms < best_spmv) {
+                best_spmv = ms;
+                destroy_spmv_plan(p);
+            } else {
+                std::swap(p, c->spmv);
+                destroy_spmv_plan(p);
+            }
+            if (c->n < 4096) break;
+        }
+    }
+    if (!c->spmv) throw HipError{hipErrorInvalidConfiguration, "no product shape could run"};
+    c->tuned_spmv_us = best_spmv * 1e3 / reps;
     JPCG_HIP(hipEventDestroy(e0));
     JPCG_HIP(hipEventDestroy(e1));
     JPCG_HIP(hipFree(xb));
     JPCG_HIP(hipFree(yb));
     std::lock_guard<std::mutex> lock(g_tune_mutex);
-    g_tune_cache[key] = TuneResult{c->npl, c->bs, c->grid, c->tuned_iter_us, c->tuned_spmv_us};
+    g_tune_cache[key] = TuneResult{c->npl,          c->bs,          c->grid,     c->tuned_iter_us, c->tuned_spmv_us,
+                                   c->spmv->npl, c->spmv->bs, c->spmv->G};
 }
 
 static void free_ctx(cg_ctx* c)
@@ -755,6 +843,7 @@ static void free_ctx(cg_ctx* c)
     if (c->graphs_std != c->graphs) destroy_graphs(c->graphs_std);
     destroy_graphs(c->graphs);
     destroy_graphs(c->graphs32);
+    destroy_spmv_plan(c->spmv);
     free_multi(c);
     if (c->mixed_dev) (void)hipFree(c->mixed_dev);
     if (c->mixed_host) (void)hipHostFree(c->mixed_host);
@@ -908,6 +997,11 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
             autotune(c);
         } else {
             c->graphs = make_graphs(c, c->form, false, c->npl, c->bs, c->grid, c->chunk);
+            // The standalone product: the solver's shape if the caller chose
+            // one, else tile width 8, block 512, two workgroups per CU.
+            const bool explicit_shape = c->opts.nnz_per_lane || c->opts.block_size || c->opts.blocks_per_cu;
+            c->spmv = explicit_shape ? make_spmv_plan(c, c->npl, c->bs, c->grid)
+                                     : make_spmv_plan(c, 8, 512, default_grid(c, 8, 512, 2));
         }
         // The mixed form needs the standard FP64 graphs (outer residual) and
         // FP32 standard graphs (inner solve) with the same tile shape.
@@ -1046,6 +1140,9 @@ int cg_get_config(cg_ctx* c, cg_config* cfg)
     cfg->form = c->form;
     cfg->tune_cached = c->tune_cached ? 1 : 0;
     cfg->col_bits = c->graphs && c->graphs->col16 ? 16 : 32;
+    cfg->spmv_nnz_per_lane = c->spmv ? c->spmv->npl : 0;
+    cfg->spmv_block_size = c->spmv ? c->spmv->bs : 0;
+    cfg->spmv_grid = c->spmv ? c->spmv->G : 0;
     cfg->spmv_us = c->tuned_spmv_us;
     cfg->iter_us = c->tuned_iter_us;
     return 0;

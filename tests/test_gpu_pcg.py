@@ -455,3 +455,26 @@ def test_solve_max_size_against_stored_oracle(cuda, form):
         assert abs(np.linalg.norm(xg) - go["x_norm"]) <= 1e-8 * go["x_norm"]
     else:
         assert rr <= 10 * go["relres_true"]
+
+
+def test_spmv_plan_shape(cuda):
+    # spmv has its own tiling and grid: tile width 8, block 512 by default, the
+    # solver's shape when the caller gives one, a timed choice with autotune;
+    # every one is the bitwise sequential product.
+    from paper_1107_0538_amd import Solver
+
+    a, _ = prob(51)
+    x = np.random.default_rng(11).uniform(-1, 1, a.n)
+    ref = oracle.spmv(a, x)
+    s = Solver(a)
+    c = s.config()
+    assert (c["spmv_nnz_per_lane"], c["spmv_block_size"]) == (8, 512) and c["spmv_grid"] >= c["grid"]
+    assert np.array_equal(s.spmv(_t(x, cuda)).cpu().numpy(), ref)
+    s = Solver(a, nnz_per_lane=4, block_size=256)
+    c = s.config()
+    assert (c["spmv_nnz_per_lane"], c["spmv_block_size"], c["spmv_grid"]) == (4, 256, c["grid"])
+    assert np.array_equal(s.spmv(_t(x, cuda)).cpu().numpy(), ref)
+    s = Solver(a, autotune=True)
+    c = s.config()
+    assert c["spmv_nnz_per_lane"] in (4, 8, 16) and c["spmv_block_size"] in (256, 512) and c["spmv_us"] > 0
+    assert np.array_equal(s.spmv(_t(x, cuda)).cpu().numpy(), ref)
