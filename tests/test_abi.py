@@ -53,3 +53,34 @@ def test_load_fails_loudly_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(capi, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError):
         capi.load()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # The ctypes mirrors of cg_csr, cg_opts, cg_info and cg_config have the
+    # header's size and field offsets (a C program compiled against
+    # include/jpcg.h prints them).
+    import os
+    import shutil
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"cg_csr": capi.cg_csr, "cg_opts": capi.cg_opts, "cg_info": capi.cg_info, "cg_config": capi.cg_config}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "jpcg.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} . %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c99", "-I", include, str(src), "-o", str(exe)], check=True)
+    out = [ln for ln in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n") if ln]
+    assert len(out) == sum(1 + len(cls._fields_) for cls in structs.values())
+    for line in out:
+        name, field, value = line.split()
+        cls = structs[name]
+        got = ctypes.sizeof(cls) if field == "." else getattr(cls, field).offset
+        assert got == int(value), (name, field, got, value)
