@@ -61,6 +61,40 @@ MEASURED_TRAFFIC = {
 }
 
 
+def hbm_probe(dev, stream, mib=512, reps=20):
+    """HBM bandwidth of a plain streaming kernel (jpcg_stream_triad, 24 bytes
+    per element) on arrays far larger than the last-level cache; the best over
+    a few grid sizes."""
+    import ctypes
+
+    import torch
+
+    from paper_1107_0538_amd import capi
+
+    lib = capi.load()
+    n = mib * 2 ** 20 // 8
+    A = torch.ones(n, dtype=torch.float64, device=dev)
+    B = torch.full((n,), 2.0, dtype=torch.float64, device=dev)
+    C = torch.empty_like(A)
+    best = (0.0, 0)
+    for grid in (256, 512, 1024, 2048, 4096):
+        call = lambda: capi.check(lib.jpcg_stream_triad(A.data_ptr(), B.data_ptr(), C.data_ptr(), 0.5, n, grid,
+                                                        ctypes.c_void_p(stream.cuda_stream)))
+        call()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        e1.synchronize()
+        gbs = 24 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        best = max(best, (gbs, grid))
+    assert float(C[0]) == 2.0 and float(C[-1]) == 2.0
+    del A, B, C
+    return {"kernel": "jpcg_stream_triad", "gbs": best[0], "grid": best[1], "array_mib": mib,
+            "frac_of_peak": best[0] / HBM_PEAK_GBS}
+
+
 def roofline(form, n, nnz, run):
     """The iteration's kernels against the HBM roofline.
 
@@ -414,6 +448,10 @@ def main():
     sb = spmv_bytes(n, nnz)
     log(f"spmv {spmv_us:.2f} us warm ({sb / spmv_us / 1e3:.0f} GB/s), cold median {statistics.median(cold):.2f} us")
 
+    # --- achievable HBM bandwidth: the library's STREAM triad on 3 x 512 MiB
+    probe = hbm_probe(dev, stream)
+    log(f"hbm probe: triad {probe['gbs']:.0f} GB/s (grid {probe['grid']})")
+
     # --- time-to-solution, both forms of the iteration
     runs = {}
     for form in ("standard", "single"):
@@ -477,7 +515,9 @@ def main():
             "kernel": f"k_spmv<{cfg['spmv_nnz_per_lane']}, {cfg['spmv_block_size']}>",
             "nnz_per_lane": cfg["spmv_nnz_per_lane"], "block_size": cfg["spmv_block_size"], "grid": cfg["spmv_grid"],
         },
-        "roofline": roofline(best, n, nnz, r),
+        "roofline": dict(roofline(best, n, nnz, r), achievable=probe["gbs"],
+                         frac_of_achievable=roofline(best, n, nnz, r)["achieved"] / probe["gbs"]),
+        "hbm_probe": probe,
         "paper_context": {"opencl_1gpu_tesla_t10_s": 0.659, "matlab_core2duo_s": 3.17,
                           "note": "different (unavailable) matrix and hardware; context only"},
     }

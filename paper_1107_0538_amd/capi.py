@@ -12,6 +12,7 @@ import re
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libjpcg.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "jpcg.h")
+PROBE_HEADER = os.path.join(os.path.dirname(PKG), "include", "jpcg_probe.h")
 
 CG_CONVERGED, CG_MAXIT, CG_BREAKDOWN = 0, 1, 2
 CG_EINVAL, CG_EDIAG, CG_ENOMEM, CG_EHIP, CG_ETIMEOUT, CG_EUNSUPPORTED = -1, -2, -3, -4, -5, -6
@@ -63,6 +64,7 @@ SIGNATURES = {
     "cg_solve_mixed": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                       ctypes.c_int32, ctypes.POINTER(cg_info)]),
     "spmv": (ctypes.c_int, [_P, _P, _P]),
+    "jpcg_stream_triad": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, _P]),
     "spmm": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "cg_solve_multi": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                       ctypes.POINTER(cg_info)]),

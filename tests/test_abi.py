@@ -21,8 +21,11 @@ def test_exports_are_c_symbols():
     out = subprocess.run(["nm", "-D", "--defined-only", capi.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
     syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
-    for n in capi.header_functions():
+    probe = capi.header_functions(capi.PROBE_HEADER)
+    assert probe == ["jpcg_stream_triad"]
+    for n in capi.header_functions() + probe:
         assert n in syms, n
+        assert n in capi.SIGNATURES, n
 
 
 def test_strerror_and_null_arguments():
