@@ -469,16 +469,21 @@ def main():
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / args.steps
         it = infos[-1]
-        assert all(i["status"] == 0 for i in infos), infos[-1]
+        if form == "standard":
+            assert all(i["status"] == 0 for i in infos), infos[-1]
         kern_s = statistics.mean(i["seconds"] for i in infos)
         checks = 1 + it["replacements"]
         sbytes = solve_bytes(n, nnz, it["iters"], checks, form)
-        runs[form] = {"wall_s": wall, "device_s": kern_s, "iters": it["iters"], "relres_true": it["relres_true"],
+        runs[form] = {"wall_s": wall, "device_s": kern_s, "iters": it["iters"], "status": it["status"],
+                      "relres_true": it["relres_true"],
                       "us_per_iter": kern_s / max(it["iters"], 1) * 1e6, "bytes": sbytes,
                       "gbs": sbytes / kern_s / 1e9, "launch": sf.config(), "x": x.cpu().numpy()}
         log(f"solve[{form}] {wall * 1e3:.3f} ms wall, {kern_s * 1e3:.3f} ms device, iters {it['iters']}, "
             f"relres {it['relres_true']:.3e}, {runs[form]['us_per_iter']:.2f} us/iter")
-    best = min(runs, key=lambda f: runs[f]["wall_s"])
+    # The value is the faster form among those that reached the tolerance
+    # (the single-reduction form can end in BREAKDOWN near the attainable
+    # accuracy, e.g. at 128^3).
+    best = min((f for f in runs if runs[f]["status"] == 0), key=lambda f: runs[f]["wall_s"])
     r = runs[best]
     wall, kern_s, sbytes = r["wall_s"], r["device_s"], r["bytes"]
     achieved = sbytes / kern_s / 1e9
@@ -531,6 +536,8 @@ def main():
             t = time.perf_counter()
             xo, io = oracle.pcg(a, b, tol=1e-10)
             ts.append(time.perf_counter() - t)
+            if ts[-1] > 5.0:
+                log(f"cpu baseline: oracle solve {len(ts)} took {ts[-1]:.1f} s")
         reps = len(ts)
         log(f"cpu baseline: {reps} oracle solves, {sum(ts):.1f} s")
         out["cpu_baseline"] = {
