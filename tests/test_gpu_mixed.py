@@ -101,3 +101,19 @@ def test_mixed_128_cubed(cuda):
     x, info = s.solve_mixed(_t(b, cuda), tol=1e-10)
     assert info["status"] == 0, info
     assert oracle.relres(a, b, x.cpu().numpy()) <= TOL_RECOMPUTED
+
+
+def test_mixed_column_index_widths_agree(cuda):
+    # The FP32 inner products read the same columns with 16- or 32-bit
+    # indices: the mixed solve is bitwise the same.
+    from paper_1107_0538_amd import Solver
+
+    a, b = prob(16)
+    out = []
+    for bits in (0, 32):
+        s = Solver(a, fp32_copy=True, col_bits=bits)
+        x, info = s.solve_mixed(_t(b, cuda), tol=1e-10)
+        assert info["status"] == 0
+        out.append((x.cpu().numpy(), info["iters"], info["outer"]))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
+    assert oracle.relres(a, b, out[0][0]) <= TOL_RECOMPUTED
