@@ -225,17 +225,25 @@ out:
 
 /*
  * The same solve in the single-reduction form of Chronopoulos and Gear
- * (J. Comput. Appl. Math. 25, 1989): s = A p is carried by a recurrence and
- * the product is applied to u = M^{-1} r, so r'u, w'u (w = A u) and r'r come
- * from one reduction per iteration; p'Ap is recovered as
- * sigma = delta - beta * gamma / alpha.  In exact arithmetic the iterates are
- * those of oracle_pcg.  Stopping rules, statuses, history and trace follow
- * oracle_pcg (trace slots hold x, r, u, p).
+ * (J. Comput. Appl. Math. 25, 1989): s = A p is carried by the recurrence
+ * s = w + beta s with w = A u, u = M^{-1} r, so the iteration needs one
+ * product, that of u.  In exact arithmetic the iterates are those of
+ * oracle_pcg.  Stopping rules, statuses, history and trace follow oracle_pcg
+ * (trace slots hold x, r, u, p).
  *
- * A residual replacement breaks the relations behind the recurred s and
- * sigma (r no longer equals r_prev - alpha s), so the step after one forms
- * p as usual and then takes s = A p and sigma = p's directly: the standard
- * form's p'Ap.
+ * p'Ap is taken as sigma = p's, the inner product of the direction with the
+ * recurred s.  (A parallel code obtains the same number from the one
+ * reduction that yields r'u, because p's expands into inner products of u,
+ * w, the previous p and the previous s.)  Chronopoulos and Gear's scalar
+ * recurrence sigma = w'u - beta r'u / alpha is not used: it assumes that the
+ * new residual is M^{-1}-orthogonal to the previous one, which a residual
+ * replacement near the attainable accuracy destroys, and the recurred sigma
+ * then turns negative for an SPD matrix.
+ *
+ * After a residual replacement the auxiliary vectors are recomputed as well
+ * (the replacement strategy for this family of forms analysed by Cools,
+ * Yetkin, Agullo, Giraud and Vanroose, SIAM J. Matrix Anal. Appl. 39, 2018):
+ * w = A u for the replaced residual, and s = A p for the new direction.
  */
 int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
                   const double *b, double *x, double tol, int maxit, int precond,
@@ -289,13 +297,13 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
         status = ORC_CONVERGED;
         goto out;
     }
-    /* u0 = M^{-1} r0, w0 = A u0, p0 = u0, s0 = w0 */
+    /* u0 = M^{-1} r0, w0 = A u0, p0 = u0, s0 = w0, sigma0 = p0's0 */
     for (int i = 0; i < n; ++i) u[i] = r[i] / diag[i];
     oracle_spmv(n, rowptr, col, val, u, w);
     double gamma = oracle_dot(n, r, u, sum_mode);
-    double sigma = oracle_dot(n, w, u, sum_mode);   /* delta_0 = p0' A p0 */
     memcpy(p, u, sizeof(double) * (size_t)n);
     memcpy(sv, w, sizeof(double) * (size_t)n);
+    double sigma = oracle_dot(n, p, sv, sum_mode);
     snapshot(trace, n, 0, x, r, u, p);
 
     int k = 0, replaced = 0;
@@ -322,9 +330,8 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
             replaced = 1;
         }
         for (int i = 0; i < n; ++i) u[i] = r[i] / diag[i];
-        oracle_spmv(n, rowptr, col, val, u, w);
+        oracle_spmv(n, rowptr, col, val, u, w);             /* w = A u */
         double gamma_new = oracle_dot(n, r, u, sum_mode);
-        double delta = oracle_dot(n, w, u, sum_mode);
         if (!(gamma_new > 0.0) || !isfinite(gamma_new)) {
             snapshot(trace, n, k, x, r, u, NULL);
             status = ORC_BREAKDOWN;
@@ -334,13 +341,12 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
         gamma = gamma_new;
         for (int i = 0; i < n; ++i) p[i] = u[i] + beta * p[i];
         if (replaced) {
-            oracle_spmv(n, rowptr, col, val, p, sv);        /* s = A p */
-            sigma = oracle_dot(n, p, sv, sum_mode);         /* sigma = p'Ap */
+            oracle_spmv(n, rowptr, col, val, p, sv);        /* s = A p, recomputed */
             replaced = 0;
         } else {
-            sigma = delta - beta * gamma_new / alpha;
             for (int i = 0; i < n; ++i) sv[i] = w[i] + beta * sv[i];
         }
+        sigma = oracle_dot(n, p, sv, sum_mode);             /* sigma = p's */
         snapshot(trace, n, k, x, r, u, p);
     }
     info->iters = k;

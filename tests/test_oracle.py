@@ -179,8 +179,10 @@ def test_self_consistency_pairwise_16():
     x1, i1 = oracle.pcg(a, b, sum_mode=1)
     assert abs(i0["iters"] - i1["iters"]) <= 2
     assert np.linalg.norm(x0 - x1) / np.linalg.norm(x0) <= 1e-8
+    # The same on the part of x beyond its constant mode (1'b / c per entry
+    # dominates ||x||): the bar the GPU solves are held to is attainable.
     xm0, xm1 = x0 - x0.mean(), x1 - x1.mean()
-    assert np.linalg.norm(xm0 - xm1) / np.linalg.norm(xm0) <= 1e-6
+    assert np.linalg.norm(xm0 - xm1) / np.linalg.norm(xm0) <= 1e-8
 
 
 def test_single_reduction_form_tracks_standard_iterates():
@@ -200,19 +202,25 @@ def test_single_reduction_form_tracks_standard_iterates():
     assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) <= 1e-8
 
 
-def test_single_reduction_form_across_replacements():
-    # Systems whose solves need residual replacements at 1e-10: after a
-    # replacement the single-reduction form takes s = A p and p'Ap directly,
-    # so it keeps tracking the standard form (within +-2 iterations, same
-    # solution to 1e-8) instead of breaking down on a recurred sigma.
-    a, _ = W.problem(14, 0)
-    fam = W.amplitude_family(n=14, count=8)
+@pytest.mark.parametrize("fam_n,first,count", [(14, 0, 8), (16, 0, 40)])
+def test_single_reduction_form_across_replacements(fam_n, first, count):
+    # Systems whose solves need residual replacements at 1e-10.  The single-
+    # reduction form takes sigma = p's (never a scalar recurrence, which turns
+    # negative on 15 of the first 40 of these 16^3 right-hand sides) and
+    # recomputes w = A u and s = A p after a replacement, so it keeps
+    # tracking the standard form: same status, within +-2 iterations, the
+    # same solution to 1e-8 with and without its constant mode.
+    a, _ = W.problem(fam_n, 0)
+    fam = W.amplitude_family(n=fam_n, count=first + count)
     reps = 0
-    for b in fam.rhs(np.arange(8)):
+    for b in fam.rhs(np.arange(first, first + count)):
         x0, i0 = oracle.pcg(a, b)
         x1, i1 = oracle.pcg(a, b, form="single")
         reps += i1["replacements"]
         assert i0["status"] == i1["status"] == oracle.CONVERGED
         assert abs(i0["iters"] - i1["iters"]) <= 2
+        assert i1["relres_true"] <= 1e-10
         assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) <= 1e-8
-    assert reps >= 4
+        xm0, xm1 = x0 - x0.mean(), x1 - x1.mean()
+        assert np.linalg.norm(xm1 - xm0) / np.linalg.norm(xm0) <= 1e-8
+    assert reps >= count // 2

@@ -31,13 +31,21 @@ MUTANTS = {
                           "rn = (oracle_dot(n, r, r, sum_mode));\n        if (hist)"),
     "p_dot_wrong_operand": ("sigma = oracle_dot(n, p, q, sum_mode)", "sigma = oracle_dot(n, q, q, sum_mode)"),
     # the single-reduction form
-    "sr_sigma_sign": ("sigma = delta - beta * gamma_new / alpha", "sigma = delta + beta * gamma_new / alpha"),
+    "sr_sigma_wrong_vector": ("sigma = oracle_dot(n, p, sv, sum_mode);             /* sigma = p's */",
+                              "sigma = oracle_dot(n, p, w, sum_mode);             /* sigma = p's */"),
+    # Chronopoulos and Gear's scalar recurrence for p'Ap in place of p's: it
+    # loses its sign after replacements near the attainable accuracy.
+    "sr_sigma_scalar_recurrence": (
+        "        }\n        sigma = oracle_dot(n, p, sv, sum_mode);             /* sigma = p's */",
+        "            sigma = oracle_dot(n, w, u, sum_mode) - beta * gamma / alpha;\n            goto next;\n"
+        "        }\n        sigma = oracle_dot(n, p, sv, sum_mode);\n    next:"),
     "sr_s_drops_beta": ("sv[i] = w[i] + beta * sv[i]", "sv[i] = w[i]"),
     "sr_residual_uses_w": ("r[i] = r[i] - alpha * sv[i]", "r[i] = r[i] - alpha * w[i]"),
-    "sr_product_of_r": ("oracle_spmv(n, rowptr, col, val, u, w);\n        double gamma_new",
-                        "oracle_spmv(n, rowptr, col, val, r, w);\n        double gamma_new"),
+    "sr_product_of_r": ("oracle_spmv(n, rowptr, col, val, u, w);             /* w = A u */",
+                        "oracle_spmv(n, rowptr, col, val, r, w);             /* w = A u */"),
     "sr_gamma_stale": ("        gamma = gamma_new;\n", "        gamma = gamma;\n"),
-    "sr_replacement_keeps_recurrence": ("        if (replaced) {", "        if (0) {"),
+    "sr_replacement_s_of_u": ("oracle_spmv(n, rowptr, col, val, p, sv);        /* s = A p, recomputed */",
+                              "oracle_spmv(n, rowptr, col, val, u, sv);        /* s = A p, recomputed */"),
 }
 
 SINGLE_FORM = {k for k in MUTANTS if k.startswith("sr_")}
@@ -77,11 +85,13 @@ def _pins_pass(form: str = "standard") -> bool:
         if not (info["status"] == oracle.CONVERGED and info["iters"] == 2):
             return False
         if form == "single":
-            # Systems that need residual replacements: the single-reduction
-            # form must converge alongside the standard one.
-            a, _ = W.problem(14, 0)
-            fam = W.amplitude_family(n=14, count=8)
-            for b in fam.rhs(np.arange(8)):
+            # Systems that need residual replacements near the attainable
+            # accuracy: the single-reduction form must converge alongside the
+            # standard one (right-hand sides 20-29 include ones on which a
+            # scalar recurrence for p'Ap loses its sign).
+            a, _ = W.problem(16, 0)
+            fam = W.amplitude_family(n=16, count=30)
+            for b in fam.rhs(np.arange(20, 30)):
                 _, i_s = oracle.pcg(a, b)
                 _, i_r = oracle.pcg(a, b, form="single")
                 if i_r["status"] != oracle.CONVERGED or abs(i_r["iters"] - i_s["iters"]) > 2:
