@@ -37,6 +37,12 @@
 
 namespace jpcg {
 
+// Per-workgroup partial sums of a solver context, in doubles per workgroup:
+// standard form 9 (setup 3, p'q 1, two parities of 2, report 1), single-
+// reduction form 2 * kSrPart + 3 (two parities, setup 2, check 1).
+constexpr int kPartPerWg = 16;
+static_assert(2 * kSrPart + 3 <= kPartPerWg && 9 <= kPartPerWg, "partials layout");
+
 // dinv_i = 1 / a_ii (Jacobi) or 1 (no preconditioner); flags a missing or
 // non-positive diagonal.
 __global__ void jacobi_kernel(int n, const int* __restrict__ rowptr, const int* __restrict__ col,
@@ -228,7 +234,7 @@ struct cg_graphs {
     int npl = 0, bs = 0, G = 0, T = 0, chunk = 0;
     int4* tiles = nullptr;
     unsigned short* col16 = nullptr;  // narrow column indices of these tiles (null: 32-bit)
-    double* part = nullptr;  // 11G doubles, laid out per form
+    double* part = nullptr;  // kPartPerWg * G doubles, laid out per form
     void* st = nullptr;      // CgState or SrState
     void* hst = nullptr;     // pinned, 4 slots
     size_t st_bytes = 0;
@@ -299,7 +305,7 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
         g->st_bytes = std::max(sizeof(CgState), sizeof(SrState));
         const size_t eb = fp32 ? sizeof(float) : sizeof(double);
         JPCG_HIP(hipMalloc(&g->tiles, sizeof(int4) * std::max(T, 1)));
-        JPCG_HIP(hipMalloc(&g->part, sizeof(double) * 11 * (size_t)G));
+        JPCG_HIP(hipMalloc(&g->part, sizeof(double) * kPartPerWg * (size_t)G));
         JPCG_HIP(hipMalloc(&g->st, g->st_bytes));
         JPCG_HIP(hipHostMalloc(&g->hst, g->st_bytes * 4, hipHostMallocDefault));
         JPCG_HIP(hipMalloc(&g->cb, eb * c->n));
@@ -341,10 +347,9 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
             sa.tm = tm;
             sa.G = G;
             sa.part[0] = g->part;
-            sa.part[1] = g->part + 3 * (size_t)G;
-            sa.part_setup = g->part + 6 * (size_t)G;
-            sa.part_chk = g->part + 8 * (size_t)G;
-            sa.part_rst = g->part + 9 * (size_t)G;
+            sa.part[1] = g->part + kSrPart * (size_t)G;
+            sa.part_setup = g->part + 2 * kSrPart * (size_t)G;
+            sa.part_chk = g->part + (2 * kSrPart + 2) * (size_t)G;
             sa.st = (SrState*)g->st;
             sa.hist = nullptr;
         }

@@ -1,25 +1,33 @@
-// Single-reduction Jacobi-PCG (the Chronopoulos-Gear form of the same
-// iteration): one kernel per iteration.
+// Single-reduction Jacobi-PCG (Chronopoulos and Gear's form of the same
+// iteration: s = A p carried by a recurrence): one kernel per iteration.
 //
 // Iteration k (the oracle's single-reduction loop, same symbols):
-//   sigma_k = delta_{k-1} - beta_{k-1} gamma_{k-1} / alpha_{k-1}, alpha_k = gamma_{k-1} / sigma_k
-//   p_{k-1} = u_{k-1} + beta_{k-1} p_{k-2},   s_{k-1} = w_{k-1} + beta_{k-1} s_{k-2}
-//   x_k = x_{k-1} + alpha_k p_{k-1},          r_k = r_{k-1} - alpha_k s_{k-1},  u_k = M^-1 r_k
-//   w_k = A u_k;  gamma_k = r_k'u_k, delta_k = w_k'u_k, ||r_k||^2   (one reduction)
-// Kernel K_k reduces the previous kernel's partials of (gamma, delta, r'r)
-// in its prologue, applies the continue-condition to r_{k-1}, and forms every
-// gathered u_k(j) on the fly from r_{k-1}, w_{k-1}, s_{k-2} and M^-1 of column
-// j with exactly the expressions the owning row lane uses, so w_k = A u_k
-// for the u_k that the row lanes store implicitly.  The gathered vectors r, w
-// and s and the Jacobi diagonal are stored together, SrQuad {r, w, s, d} per
-// row, in two arrays used by iteration parity (one 32-byte gather per
-// nonzero; kernels store whole quads where they can); p and x update in place
-// (no other row reads them).
+//   sigma_k = p_{k-1}' s_{k-1},  alpha_k = gamma_{k-1} / sigma_k, where
+//     p_{k-1} = u_{k-1} + beta_{k-1} p_{k-2},  s_{k-1} = w_{k-1} + beta_{k-1} s_{k-2}
+//   x_k = x_{k-1} + alpha_k p_{k-1},  r_k = r_{k-1} - alpha_k s_{k-1},  u_k = M^-1 r_k
+//   w_k = A u_k;  one reduction of
+//     gamma_k = r_k'u_k, delta_k = w_k'u_k, ||r_k||^2,
+//     e_k = u_k's_{k-1} + p_{k-1}'w_k, f_k = p_{k-1}'s_{k-1}
+// so that the next kernel obtains p_k's_k without a second reduction:
+//     sigma_{k+1} = delta_k + beta_k e_k + beta_k^2 f_k,  beta_k = gamma_k / gamma_{k-1}.
+// (Chronopoulos and Gear's scalar recurrence sigma = delta - beta gamma / alpha
+// assumes r_k'u_{k-1} = 0, which a residual replacement near the attainable
+// accuracy destroys; it then turns negative for an SPD matrix.)
+// Kernel K_k reduces the previous kernel's partials in its prologue, applies
+// the continue-condition to r_{k-1}, and forms every gathered u_k(j) on the
+// fly from r_{k-1}, w_{k-1}, s_{k-2} and M^-1 of column j with exactly the
+// expressions the owning row lane uses, so w_k = A u_k for the u_k that the
+// row lanes store implicitly.  The gathered vectors r, w and s and the Jacobi
+// diagonal are stored together, SrQuad {r, w, s, d} per row, in two arrays
+// used by iteration parity (one 32-byte gather per nonzero; kernels store
+// whole quads where they can); p and x update in place (no other row reads
+// them).
 //
-// After a residual replacement the recurrences behind sigma no longer hold:
-// the restart kernel recomputes s = A p exactly and the partials of u'(A p)
-// and p'(A p), and the next kernel takes sigma = p_new' A p_new expanded as
-// delta + 2 beta u'(A p) + beta^2 p'(A p).
+// After a residual replacement the auxiliary vectors are recomputed from
+// their definitions (the replacement strategy for these forms analysed by
+// Cools, Yetkin, Agullo, Giraud and Vanroose, 2018): the restart kernel forms
+// w = A u for the replaced r and s = A p_{k-1}, with the same five partials,
+// and the next kernel proceeds as after any other iteration.
 #pragma once
 
 #include "tiles.hpp"
@@ -34,11 +42,12 @@ struct SrState {
     int replacements;
     double nb, thr;
     double gam[2];    // gam[P] = gamma_{k-1}, written by K_k (P = k % 2)
-    double alpha[2];  // alpha[P] = alpha_k, written by K_k
-    int rst[2];       // rst[P]: the state in parity P follows a replacement
     double rr;        // ||r||^2 at the last continue-condition test
     double rr_true;   // ||b - A x||^2 of the returned x
 };
+
+// Partials per workgroup and iteration: gamma, delta, ||r||^2, e, f.
+constexpr int kSrPart = 5;
 
 struct alignas(32) SrQuad {
     double r, w, s, d;
@@ -56,10 +65,9 @@ struct SrArgs {
     double* p;
     TileMap tm;
     int G;
-    double* part[2];     // [G][3]: gamma, delta, r'r from the kernel of parity P
+    double* part[2];     // [G][kSrPart]: gamma, delta, r'r, e, f from the kernel of parity P
     double* part_setup;  // [G][2]: r'r, b'b of r0
     double* part_chk;    // [G][1]: ||b - A x||^2 (check and report)
-    double* part_rst;    // [G][2]: u'(A p), p'(A p) after a replacement
     SrState* st;
     double* hist;
 };
@@ -114,8 +122,6 @@ __global__ __launch_bounds__(BS) void k_sr_first(SrArgs a, double tol, int maxit
     if (sr_leader(a)) {
         st->kk[0] = 0;
         st->kk[1] = 0;
-        st->rst[0] = 0;
-        st->rst[1] = 0;
         st->k_done = 0;
         st->maxit = maxit;
         st->replacements = 0;
@@ -139,7 +145,8 @@ __global__ __launch_bounds__(BS) void k_sr_first(SrArgs a, double tol, int maxit
     }
     if (sqrt(rr) <= thr) return;
     SrQuad* __restrict__ q0 = a.qd[0];
-    double v[3] = {0.0, 0.0, 0.0};
+    // p and s start at zero, so e = f = 0 and sigma_1 = delta_0.
+    double v[kSrPart] = {0.0, 0.0, 0.0, 0.0, 0.0};
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
         // Gathers read only the r and d halves; row steps write only w.
@@ -153,7 +160,7 @@ __global__ __launch_bounds__(BS) void k_sr_first(SrArgs a, double tol, int maxit
             v[2] += rd.a * rd.a;
         },
         NoPrologue{});
-    block_partials<BS, 3>(v, sh.red, a.part[0], sr_logical(a));
+    block_partials<BS, kSrPart>(v, sh.red, a.part[0], sr_logical(a));
 }
 
 // K_k, parity P = k % 2.
@@ -169,20 +176,19 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
     double alpha = 0.0, beta = 0.0, gam_prev = 0.0;
     int km1 = 0;
     bool go = false;
-    __shared__ double s_g[3];
+    __shared__ double s_g[kSrPart];
     auto prologue = [&]() -> bool {
-        const int stop = st->stop, maxit = st->maxit, rst = st->rst[Q];
+        const int stop = st->stop, maxit = st->maxit;
         km1 = st->kk[Q];
-        const double thr = st->thr, nb = st->nb, gam2 = st->gam[Q], alpha1 = st->alpha[Q];
+        const double thr = st->thr, nb = st->nb, gam2 = st->gam[Q];
         // Wave 0 reduces the partials for the workgroup (every wave calls the
         // prologue exactly once, so the barrier is met by all of them).
         if (threadIdx.x < kWave) {
-            double g0[3];
-            wave_grid_sum<3>(a.part[Q], a.G, g0);
+            double g0[kSrPart];
+            wave_grid_sum<kSrPart>(a.part[Q], a.G, g0);
             if (threadIdx.x == 0) {
-                s_g[0] = g0[0];
-                s_g[1] = g0[1];
-                s_g[2] = g0[2];
+#pragma unroll
+                for (int j = 0; j < kSrPart; ++j) s_g[j] = g0[j];
             }
         }
         __syncthreads();
@@ -202,13 +208,8 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
         else {
             if (km1 > 0) {
                 beta = gam / gam2;
-                if (rst) {  // s was recomputed as A p after a replacement
-                    double e[2];
-                    wave_grid_sum<2>(a.part_rst, a.G, e);
-                    sigma = delta + 2.0 * beta * e[0] + beta * beta * e[1];
-                } else {
-                    sigma = delta - beta * gam / alpha1;
-                }
+                // p's with p = u + beta p_old, s = w + beta s_old, expanded.
+                sigma = delta + beta * s_g[3] + beta * beta * s_g[4];
             }
             if (!(sigma > 0.0) || !isfinite(sigma)) code = STOP_BREAKDOWN;
         }
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
         go = true;
         return true;
     };
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[kSrPart] = {0.0, 0.0, 0.0, 0.0, 0.0};
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), sh.prod + (threadIdx.x / kWave) * (kWave * NPL),
         [&](int j) { return qold[j]; },
@@ -245,15 +246,15 @@ __global__ __launch_bounds__(BS) void k_sr_iter(SrArgs a, int P)
             v[0] += ri * ui;
             v[1] += wi * ui;
             v[2] += ri * ri;
+            v[3] += ui * si + pi * wi;
+            v[4] += pi * si;
         },
         prologue);
     if (!go) return;  // the same decision in every wave of every workgroup
-    block_partials<BS, 3>(v, sh.red, a.part[P], sr_logical(a));
+    block_partials<BS, kSrPart>(v, sh.red, a.part[P], sr_logical(a));
     if (lead) {
         st->kk[P] = km1 + 1;
         st->gam[P] = gam_prev;
-        st->alpha[P] = alpha;
-        st->rst[P] = 0;
     }
 }
 
@@ -298,9 +299,14 @@ __global__ __launch_bounds__(BS) void k_sr_decide(SrArgs a, int report)
     }
 }
 
-// After a replacement: w = A M^-1 r for the replaced r in qd[P], with the
-// partials of (gamma, delta, r'r) in part[P] for the next iteration; then
-// s = A p into qd[P].s with the partials of u'(A p) and p'(A p) in part_rst.
+// After a replacement at iteration k (parity P): w_k = A M^-1 r_k for the
+// replaced r in qd[P].w and s = A p_{k-1} in qd[P].s, with the five partials
+// of the iteration kernel (gamma, delta, r'r, u'(A p) + p'w, p'(A p)) in
+// part[P], so the next kernel continues as after an ordinary iteration.
+struct Rdp {
+    double r, d, p;
+};
+
 template <int NPL, int BS>
 __global__ __launch_bounds__(BS) void k_sr_restart(SrArgs a, int P)
 {
@@ -308,34 +314,32 @@ __global__ __launch_bounds__(BS) void k_sr_restart(SrArgs a, int P)
     SrQuad* __restrict__ q = a.qd[P];
     const double* __restrict__ p = a.p;
     double* prod = sh.prod + (threadIdx.x / kWave) * (kWave * NPL);
-    double v[3] = {0.0, 0.0, 0.0};
+    double v[kSrPart] = {0.0, 0.0, 0.0, 0.0, 0.0};
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), prod,
         [&](int j) { return Pair2{q[j].r, q[j].d}; }, [&](Pair2 rd) { return rd.b * rd.a; },
-        [&](int i) { return Pair2{q[i].r, q[i].d}; },
-        [&](int i, double wi, Pair2 rd) {
-            const double ui = rd.b * rd.a;
+        [&](int i) { return Rdp{q[i].r, q[i].d, p[i]}; },
+        [&](int i, double wi, Rdp o) {
+            const double ui = o.d * o.r;
             q[i].w = wi;
-            v[0] += rd.a * ui;
+            v[0] += o.r * ui;
             v[1] += wi * ui;
-            v[2] += rd.a * rd.a;
+            v[2] += o.r * o.r;
+            v[3] += o.p * wi;
         },
         NoPrologue{});
     // The second product's gathers read only p, and its row steps write only
     // the s half of the quads, so the first product's w stores cannot race.
-    double e[2] = {0.0, 0.0};
     tile_rows<NPL, double>(
         a.rowptr, a.col, a.val, a.tm, sr_logical(a), prod, [&](int j) { return p[j]; }, Ident<double>{},
         [&](int i) { return Pair2{p[i], q[i].d * q[i].r}; },
         [&](int i, double si, Pair2 pu) {
             q[i].s = si;
-            e[0] += pu.b * si;
-            e[1] += pu.a * si;
+            v[3] += pu.b * si;
+            v[4] += pu.a * si;
         },
         NoPrologue{});
-    block_partials<BS, 3>(v, sh.red, a.part[P], sr_logical(a));
-    block_partials<BS, 2>(e, sh.red, a.part_rst, sr_logical(a));
-    if (sr_leader(a)) a.st->rst[P] = 1;
+    block_partials<BS, kSrPart>(v, sh.red, a.part[P], sr_logical(a));
 }
 
 }  // namespace jpcg

@@ -32,7 +32,12 @@ def main():
         out["forms"][form] = {"iters": int(info["iters"]), "status": int(info["status"]),
                               "replacements": int(info["replacements"]),
                               "relres_true": float(info["relres_true"]),
-                              "x_norm": float(np.linalg.norm(x)), "x_rows": [float(v) for v in x[rows]]}
+                              "x_norm": float(np.linalg.norm(x)), "x_rows": [float(v) for v in x[rows]],
+                              # the constant mode dominates x: the mean and the
+                              # mean-removed values let a test see the rest
+                              "x_mean": float(np.mean(x)),
+                              "x_centred_norm": float(np.linalg.norm(x - np.mean(x))),
+                              "x_rows_centred": [float(v) for v in x[rows] - np.mean(x)]}
         print(form, info, flush=True)
     with open(os.path.join(HERE, "q1hex128_oracle.json"), "w") as f:
         json.dump(out, f, indent=0)
