@@ -6,7 +6,9 @@ benchmark's CPU-baseline leg may import this package; the GPU library and its
 Python binding never do, and this package never imports them.
 
 - `pcg`, `spmv`, `residual`, `dot`: FP64 C code in pcg_oracle.c, loaded
-  through ctypes (built with gcc, -O2 -ffp-contract=off).
+  through ctypes (built with gcc, -O2 -ffp-contract=off).  A second build of
+  the same source with -fopenmp (`pcg(..., parallel=True)`) exists only to
+  time the oracle on all host cores; its dot products sum in another order.
 - `mlp`: an FP64 numpy multilayer perceptron (forward, backward, Adam).
 - `pod`: proper orthogonal decomposition by the method of snapshots.
 """
@@ -21,6 +23,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "pcg_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 CONVERGED, MAXIT, BREAKDOWN = 0, 1, 2
 EINVAL, EDIAG, ENOMEM = -1, -2, -3
@@ -50,30 +53,57 @@ def build(out: str = LIB) -> str:
     return out
 
 
-_lib = None
+def build_omp(out: str = LIB_OMP) -> str:
+    """The same source with OpenMP, for timing the oracle on every host core."""
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           SRC, "-o", out + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
 
 
-def lib():
-    """Load the oracle library, building it first if nothing is built."""
+_libs = {}
+_lib = None  # the plain build (tests swap it for mutated copies)
+
+
+def _bind(L):
+    P = ctypes.c_void_p
+    L.oracle_spmv.argtypes = [ctypes.c_int, P, P, P, P, P]
+    L.oracle_spmv.restype = ctypes.c_int
+    L.oracle_dot.argtypes = [ctypes.c_int, P, P, ctypes.c_int]
+    L.oracle_dot.restype = ctypes.c_double
+    L.oracle_residual.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+    L.oracle_residual.restype = ctypes.c_double
+    L.oracle_pcg.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, ctypes.c_int,
+                             ctypes.c_int, ctypes.c_int, ctypes.POINTER(OracleInfo), P, P]
+    L.oracle_pcg.restype = ctypes.c_int
+    L.oracle_pcg_sr.argtypes = L.oracle_pcg.argtypes
+    L.oracle_pcg_sr.restype = ctypes.c_int
+    L.oracle_threads.argtypes = []
+    L.oracle_threads.restype = ctypes.c_int
+    return L
+
+
+def lib(parallel: bool = False):
+    """Load the oracle library (the OpenMP build with parallel=True),
+    building it first if nothing is built."""
     global _lib
+    if parallel:
+        if "omp" not in _libs:
+            if not os.path.exists(LIB_OMP):
+                build_omp()
+            _libs["omp"] = _bind(ctypes.CDLL(LIB_OMP))
+        return _libs["omp"]
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = ctypes.CDLL(LIB)
-        P = ctypes.c_void_p
-        L.oracle_spmv.argtypes = [ctypes.c_int, P, P, P, P, P]
-        L.oracle_spmv.restype = ctypes.c_int
-        L.oracle_dot.argtypes = [ctypes.c_int, P, P, ctypes.c_int]
-        L.oracle_dot.restype = ctypes.c_double
-        L.oracle_residual.argtypes = [ctypes.c_int, P, P, P, P, P, P]
-        L.oracle_residual.restype = ctypes.c_double
-        L.oracle_pcg.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, ctypes.c_int,
-                                 ctypes.c_int, ctypes.c_int, ctypes.POINTER(OracleInfo), P, P]
-        L.oracle_pcg.restype = ctypes.c_int
-        L.oracle_pcg_sr.argtypes = L.oracle_pcg.argtypes
-        L.oracle_pcg_sr.restype = ctypes.c_int
-        _lib = L
+        _lib = _bind(ctypes.CDLL(LIB))
     return _lib
+
+
+def threads(parallel: bool = False) -> int:
+    """Threads a solve of that build uses (1 for the plain build)."""
+    return lib(parallel).oracle_threads()
 
 
 def _p(a):
@@ -122,11 +152,13 @@ def relres(a, b, x) -> float:
 
 
 def pcg(a, b, x0=None, tol: float = 1e-10, maxit: int = 0, precond: str = "jacobi",
-        sum_mode: int = 0, history: bool = False, trace: bool = False, form: str = "standard"):
+        sum_mode: int = 0, history: bool = False, trace: bool = False, form: str = "standard",
+        parallel: bool = False):
     """Run the oracle solve.  Returns (x, info dict[, hist][, trace]).
 
     form: "standard" (two reductions per iteration) or "single" (the
     single-reduction Chronopoulos-Gear form of the same iteration).
+    parallel: run the OpenMP build (timing only).
     """
     rowptr, col, val = _csr_arrays(a)
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -136,7 +168,8 @@ def pcg(a, b, x0=None, tol: float = 1e-10, maxit: int = 0, precond: str = "jacob
     tr = np.full((mi + 1, 4, a.n), np.nan) if trace else None
     info = OracleInfo()
     pc = {"none": 0, "jacobi": 1}[precond]
-    fn = {"standard": lib().oracle_pcg, "single": lib().oracle_pcg_sr}[form]
+    L = lib(parallel)
+    fn = {"standard": L.oracle_pcg, "single": L.oracle_pcg_sr}[form]
     fn(a.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), tol, mi, pc, sum_mode,
        ctypes.byref(info), _p(hist) if history else None, _p(tr) if trace else None)
     d = info.as_dict()

@@ -30,6 +30,30 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Built plainly, the oracle is single-threaded and these expand to nothing.
+ * A second build with -fopenmp (used only to time the CPU on all its cores)
+ * splits the row loop of the product and the element-wise loops across
+ * threads, which leaves their results unchanged, and the sequential dot
+ * product into per-thread partial sums, which changes its rounding order. */
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_PAR _Pragma("omp parallel for schedule(static)")
+#define ORC_PAR_SUM _Pragma("omp parallel for schedule(static) reduction(+:s)")
+#else
+#define ORC_PAR
+#define ORC_PAR_SUM
+#endif
+
+/* Threads a solve uses: 1 in the plain build. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 #define ORC_CONVERGED 0
 #define ORC_MAXIT 1
 #define ORC_BREAKDOWN 2
@@ -51,6 +75,7 @@ int oracle_spmv(int n, const int *rowptr, const int *col, const double *val,
                 const double *x, double *y)
 {
     if (n < 0 || !rowptr || !col || !val || !x || !y) return ORC_EINVAL;
+    ORC_PAR
     for (int i = 0; i < n; ++i) {
         double s = 0.0;
         for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) s += val[k] * x[col[k]];
@@ -76,6 +101,7 @@ double oracle_dot(int n, const double *a, const double *b, int mode)
     if (n <= 0) return 0.0;
     if (mode == 1) return sum_pairwise(a, b, 0, (size_t)n);
     double s = 0.0;
+    ORC_PAR_SUM
     for (int i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
 }
@@ -85,6 +111,7 @@ double oracle_residual(int n, const int *rowptr, const int *col, const double *v
                        const double *b, const double *x, double *r)
 {
     if (oracle_spmv(n, rowptr, col, val, x, r) != 0) return -1.0;
+    ORC_PAR
     for (int i = 0; i < n; ++i) r[i] = b[i] - r[i];
     return sqrt(oracle_dot(n, r, r, 0));
 }
@@ -146,6 +173,7 @@ int oracle_pcg(int n, const int *rowptr, const int *col, const double *val,
 
     double nb = sqrt(oracle_dot(n, b, b, sum_mode));
     if (nb == 0.0) {
+        ORC_PAR
         for (int i = 0; i < n; ++i) x[i] = 0.0;
         info->relres_recur = 0.0;
         info->relres_true = 0.0;
@@ -157,6 +185,7 @@ int oracle_pcg(int n, const int *rowptr, const int *col, const double *val,
 
     /* r0 = b - A x0 */
     oracle_spmv(n, rowptr, col, val, x, r);
+    ORC_PAR
     for (int i = 0; i < n; ++i) r[i] = b[i] - r[i];
     double rn = sqrt(oracle_dot(n, r, r, sum_mode));
     if (hist) hist[0] = rn / nb;
@@ -168,6 +197,7 @@ int oracle_pcg(int n, const int *rowptr, const int *col, const double *val,
         goto out;
     }
     /* z0 = M^{-1} r0, p0 = z0, rho0 = r0' z0 */
+    ORC_PAR
     for (int i = 0; i < n; ++i) z[i] = r[i] / diag[i];
     memcpy(p, z, sizeof(double) * (size_t)n);
     double rho = oracle_dot(n, r, z, sum_mode);
@@ -179,7 +209,9 @@ int oracle_pcg(int n, const int *rowptr, const int *col, const double *val,
         double sigma = oracle_dot(n, p, q, sum_mode);       /* sigma = p'q   */
         if (!(sigma > 0.0) || !isfinite(sigma)) { status = ORC_BREAKDOWN; break; }
         double alpha = rho / sigma;
+        ORC_PAR
         for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        ORC_PAR
         for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
         ++k;
         rn = sqrt(oracle_dot(n, r, r, sum_mode));
@@ -187,6 +219,7 @@ int oracle_pcg(int n, const int *rowptr, const int *col, const double *val,
         info->relres_recur = rn / nb;
         if (rn <= thr) {                                    /* continue-condition */
             oracle_spmv(n, rowptr, col, val, x, q);
+            ORC_PAR
             for (int i = 0; i < n; ++i) q[i] = b[i] - q[i];
             double tn = sqrt(oracle_dot(n, q, q, sum_mode));
             if (tn <= thr) {
@@ -197,6 +230,7 @@ int oracle_pcg(int n, const int *rowptr, const int *col, const double *val,
             memcpy(r, q, sizeof(double) * (size_t)n);       /* residual replacement */
             info->replacements += 1;
         }
+        ORC_PAR
         for (int i = 0; i < n; ++i) z[i] = r[i] / diag[i];
         double rho_new = oracle_dot(n, r, z, sum_mode);
         if (!(rho_new > 0.0) || !isfinite(rho_new)) {
@@ -206,6 +240,7 @@ int oracle_pcg(int n, const int *rowptr, const int *col, const double *val,
         }
         double beta = rho_new / rho;
         rho = rho_new;
+        ORC_PAR
         for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         snapshot(trace, n, k, x, r, z, p);
     }
@@ -213,6 +248,7 @@ int oracle_pcg(int n, const int *rowptr, const int *col, const double *val,
     {
         /* Reported, not part of the method: the true residual of the returned x. */
         oracle_spmv(n, rowptr, col, val, x, q);
+        ORC_PAR
         for (int i = 0; i < n; ++i) q[i] = b[i] - q[i];
         info->relres_true = sqrt(oracle_dot(n, q, q, sum_mode)) / nb;
     }
@@ -280,6 +316,7 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
 
     double nb = sqrt(oracle_dot(n, b, b, sum_mode));
     if (nb == 0.0) {
+        ORC_PAR
         for (int i = 0; i < n; ++i) x[i] = 0.0;
         if (hist) hist[0] = 0.0;
         status = ORC_CONVERGED;
@@ -287,6 +324,7 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
     }
     double thr = tol * nb;
     oracle_spmv(n, rowptr, col, val, x, r);
+    ORC_PAR
     for (int i = 0; i < n; ++i) r[i] = b[i] - r[i];
     double rn = sqrt(oracle_dot(n, r, r, sum_mode));
     if (hist) hist[0] = rn / nb;
@@ -298,6 +336,7 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
         goto out;
     }
     /* u0 = M^{-1} r0, w0 = A u0, p0 = u0, s0 = w0, sigma0 = p0's0 */
+    ORC_PAR
     for (int i = 0; i < n; ++i) u[i] = r[i] / diag[i];
     oracle_spmv(n, rowptr, col, val, u, w);
     double gamma = oracle_dot(n, r, u, sum_mode);
@@ -310,7 +349,9 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
     while (k < maxit) {
         if (!(sigma > 0.0) || !isfinite(sigma)) { status = ORC_BREAKDOWN; break; }
         double alpha = gamma / sigma;
+        ORC_PAR
         for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        ORC_PAR
         for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * sv[i];
         ++k;
         rn = sqrt(oracle_dot(n, r, r, sum_mode));
@@ -318,6 +359,7 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
         info->relres_recur = rn / nb;
         if (rn <= thr) {                                    /* continue-condition */
             oracle_spmv(n, rowptr, col, val, x, t);
+            ORC_PAR
             for (int i = 0; i < n; ++i) t[i] = b[i] - t[i];
             double tn = sqrt(oracle_dot(n, t, t, sum_mode));
             if (tn <= thr) {
@@ -329,6 +371,7 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
             info->replacements += 1;
             replaced = 1;
         }
+        ORC_PAR
         for (int i = 0; i < n; ++i) u[i] = r[i] / diag[i];
         oracle_spmv(n, rowptr, col, val, u, w);             /* w = A u */
         double gamma_new = oracle_dot(n, r, u, sum_mode);
@@ -339,11 +382,13 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
         }
         double beta = gamma_new / gamma;
         gamma = gamma_new;
+        ORC_PAR
         for (int i = 0; i < n; ++i) p[i] = u[i] + beta * p[i];
         if (replaced) {
             oracle_spmv(n, rowptr, col, val, p, sv);        /* s = A p, recomputed */
             replaced = 0;
         } else {
+            ORC_PAR
             for (int i = 0; i < n; ++i) sv[i] = w[i] + beta * sv[i];
         }
         sigma = oracle_dot(n, p, sv, sum_mode);             /* sigma = p's */
@@ -351,6 +396,7 @@ int oracle_pcg_sr(int n, const int *rowptr, const int *col, const double *val,
     }
     info->iters = k;
     oracle_spmv(n, rowptr, col, val, x, t);
+    ORC_PAR
     for (int i = 0; i < n; ++i) t[i] = b[i] - t[i];
     info->relres_true = sqrt(oracle_dot(n, t, t, sum_mode)) / nb;
 
