@@ -46,7 +46,8 @@ enum {
     CG_ENOMEM = -3,      /* device or host allocation failed                         */
     CG_EHIP = -4,        /* a HIP runtime call failed                                */
     CG_ETIMEOUT = -5,    /* a device-side wait exceeded its limit; the kernel left   */
-    CG_EUNSUPPORTED = -6 /* option not available for this context                    */
+    CG_EUNSUPPORTED = -6, /* option not available for this context                   */
+    CG_ESCRATCH = -7     /* request larger than a no-allocation call's fixed scratch */
 };
 
 enum { CG_MEM_HOST = 0, CG_MEM_DEVICE = 1 };
@@ -278,6 +279,20 @@ int dense_gram(const double *A, int64_t n, int32_t ka, int64_t lda, const double
                double *C, void *hip_stream);
 int dense_gemm(const double *A, int64_t n, int32_t k, int64_t lda, const double *W, int32_t m, double *C,
                int64_t ldc, void *hip_stream);
+/* dense_gram_noalloc: dense_gram for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and result (bitwise equal to
+ * dense_gram); the chunk partials live in a fixed 32 MiB device buffer that
+ * the library holds on each device it runs on until the process ends, and the
+ * call allocates nothing.  Limit: ceil(n / 2048) * ka * kb <= 4194304
+ * (e.g. ka = kb = 64 up to n = 2097152); larger requests return CG_ESCRATCH
+ * before any work is enqueued.  Runs on the current device, which must own
+ * hip_stream (else CG_EINVAL).  Every call on a device shares that buffer:
+ * calls that overlap on one device (other streams, other threads) race and
+ * must be serialised by the caller.  Asynchronous; returns 0, CG_EINVAL,
+ * CG_ESCRATCH, CG_EUNSUPPORTED (device index >= 64) or CG_EHIP. */
+int dense_gram_noalloc(const double *A, int64_t n, int32_t ka, int64_t lda, const double *B, int32_t kb,
+                       int64_t ldb, double *C, void *hip_stream);
 /* Decode POD coefficients into start vectors: X (n x nb, row-major) = Phi c'
  * with Phi n x k (ldphi, FP64), coef nb x k (row-major, FP32: the network's
  * output layout) and c_jl = scale[l] * coef_jl + shift[l] in FP64 (scale and

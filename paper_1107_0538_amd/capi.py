@@ -15,7 +15,8 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "jpcg.h")
 PROBE_HEADER = os.path.join(os.path.dirname(PKG), "include", "jpcg_probe.h")
 
 CG_CONVERGED, CG_MAXIT, CG_BREAKDOWN = 0, 1, 2
-CG_EINVAL, CG_EDIAG, CG_ENOMEM, CG_EHIP, CG_ETIMEOUT, CG_EUNSUPPORTED = -1, -2, -3, -4, -5, -6
+CG_EINVAL, CG_EDIAG, CG_ENOMEM, CG_EHIP, CG_ETIMEOUT, CG_EUNSUPPORTED, CG_ESCRATCH = -1, -2, -3, -4, -5, -6, -7
+GRAM_SCRATCH_DOUBLES, GRAM_CHUNK = 4 << 20, 2048
 CG_MEM_HOST, CG_MEM_DEVICE = 0, 1
 CG_PRECOND_DEFAULT, CG_PRECOND_JACOBI, CG_PRECOND_NONE = 0, 1, 2
 CG_FORM_STANDARD, CG_FORM_SINGLE_REDUCTION = 0, 1
@@ -78,6 +79,8 @@ SIGNATURES = {
     "cg_batch_destroy": (None, [_P]),
     "dense_gram": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int32,
                                   ctypes.c_int64, _P, _P]),
+    "dense_gram_noalloc": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int32,
+                                          ctypes.c_int64, _P, _P]),
     "dense_gemm": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int32, _P,
                                   ctypes.c_int64, _P]),
     "pod_decode": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int32, _P, _P,

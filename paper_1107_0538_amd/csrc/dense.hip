@@ -12,6 +12,7 @@
 // Each thread owns a 4 x 4 block of outputs; operands are staged through LDS.
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "context.hpp"
 
@@ -152,6 +153,48 @@ __global__ __launch_bounds__(256) void k_decode(const double* __restrict__ Phi, 
     }
 }
 
+// Fixed scratch of the no-allocation Gram (the per-chunk partials): one copy
+// per device, held until the process ends.  Host code never passes this name
+// to a kernel; it uses the address hipGetSymbolAddress returns on the device.
+constexpr size_t kGramScratchDoubles = (size_t)4 << 20;  // 32 MiB
+static __device__ __align__(256) double scratch[kGramScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (which must be current),
+// looked up once per device.
+int scratch_address(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return CG_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CG_EHIP;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+constexpr int64_t kGramChunk = 2048;
+
+int64_t gram_parts(int64_t n) { return std::max<int64_t>(1, (n + kGramChunk - 1) / kGramChunk); }
+
+// C = A' B through the partials buffer `part` (gram_parts(n) * ka * kb doubles).
+void gram_launch(const double* A, int64_t n, int ka, int64_t lda, const double* B, int kb, int64_t ldb,
+                 double* C, double* part, hipStream_t st)
+{
+    const int nparts = (int)gram_parts(n);
+    dim3 grid((ka + kT - 1) / kT, (kb + kT - 1) / kT, nparts);
+    k_gram_partial<<<grid, 256, 0, st>>>(A, n, ka, lda, B, kb, ldb, part, kGramChunk);
+    JPCG_HIP(hipGetLastError());
+    const int64_t count = (int64_t)ka * kb;
+    k_sum_partials<<<(int)std::min<int64_t>(4096, (count + 255) / 256), 256, 0, st>>>(part, nparts, count, C);
+    JPCG_HIP(hipGetLastError());
+}
+
 }  // namespace jpcg
 
 using namespace jpcg;
@@ -164,20 +207,37 @@ int dense_gram(const double* A, int64_t n, int32_t ka, int64_t lda, const double
     if (!A || !B || !C || n < 0 || ka <= 0 || kb <= 0 || lda < ka || ldb < kb) return CG_EINVAL;
     try {
         hipStream_t st = (hipStream_t)stream;
-        const int64_t chunk = 2048;
-        const int nparts = (int)std::max<int64_t>(1, (n + chunk - 1) / chunk);
         double* part = nullptr;
-        JPCG_HIP(hipMallocAsync((void**)&part, sizeof(double) * (size_t)nparts * ka * kb, st));
-        dim3 grid((ka + kT - 1) / kT, (kb + kT - 1) / kT, nparts);
-        k_gram_partial<<<grid, 256, 0, st>>>(A, n, ka, lda, B, kb, ldb, part, chunk);
-        JPCG_HIP(hipGetLastError());
-        const int64_t count = (int64_t)ka * kb;
-        k_sum_partials<<<(int)std::min<int64_t>(4096, (count + 255) / 256), 256, 0, st>>>(part, nparts, count, C);
-        JPCG_HIP(hipGetLastError());
+        JPCG_HIP(hipMallocAsync((void**)&part, sizeof(double) * (size_t)gram_parts(n) * ka * kb, st));
+        gram_launch(A, n, ka, lda, B, kb, ldb, C, part, st);
         JPCG_HIP(hipFreeAsync(part, st));
         return 0;
     } catch (const HipError& e) {
         return e.code == hipErrorOutOfMemory ? CG_ENOMEM : CG_EHIP;
+    }
+}
+
+int dense_gram_noalloc(const double* A, int64_t n, int32_t ka, int64_t lda, const double* B, int32_t kb,
+                       int64_t ldb, double* C, void* stream)
+{
+    if (!A || !B || !C || n < 0 || ka <= 0 || kb <= 0 || lda < ka || ldb < kb) return CG_EINVAL;
+    if ((uint64_t)gram_parts(n) * (uint64_t)ka * (uint64_t)kb > kGramScratchDoubles) return CG_ESCRATCH;
+    try {
+        hipStream_t st = (hipStream_t)stream;
+        int dev = -1;
+        JPCG_HIP(hipGetDevice(&dev));
+        if (st) {
+            int sdev = -1;
+            JPCG_HIP(hipStreamGetDevice(st, &sdev));
+            if (sdev != dev) return CG_EINVAL;
+        }
+        double* part = nullptr;
+        const int rc = scratch_address(dev, &part);
+        if (rc) return rc;
+        gram_launch(A, n, ka, lda, B, kb, ldb, C, part, st);
+        return 0;
+    } catch (const HipError&) {
+        return CG_EHIP;
     }
 }
 

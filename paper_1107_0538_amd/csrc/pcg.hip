@@ -885,6 +885,7 @@ const char* cg_strerror(int code)
         case CG_EHIP: return "HIP runtime error";
         case CG_ETIMEOUT: return "device wait timed out";
         case CG_EUNSUPPORTED: return "unsupported option";
+        case CG_ESCRATCH: return "request exceeds the fixed scratch buffer of a no-allocation call";
         default: return "unknown status";
     }
 }
