@@ -224,3 +224,43 @@ def test_single_reduction_form_across_replacements(fam_n, first, count):
         xm0, xm1 = x0 - x0.mean(), x1 - x1.mean()
         assert np.linalg.norm(xm1 - xm0) / np.linalg.norm(xm0) <= 1e-8
     assert reps >= count // 2
+
+
+def _residual_reversed_rows(a, b, x):
+    """b - A x with every row summed from its last stored entry to its first."""
+    prod = a.val * x[a.col]
+    lens = np.diff(a.rowptr)
+    acc = np.zeros(a.n)
+    for k in range(int(lens.max())):
+        has = lens > k
+        acc[has] += prod[a.rowptr[1:][has] - 1 - k]
+    return b - acc
+
+
+@pytest.mark.slow
+def test_learned_family_attainable_accuracy():
+    # Why the learned family is solved to 1e-8: b = M f of narrow smooth
+    # sources is small against A x, whose constant mode is 1'b / c with
+    # c = 1e-3.  The FP64 true residual b - A x of such x is then determined
+    # only to about u || |A| |x| || (the rounding of the row sums), which is
+    # of the order of 1e-10 ||b|| itself: two summation orders of the same
+    # residual already differ by more than a tenth of 1e-10 ||b||, and the
+    # oracle, with residual replacement, stays above 1e-10 for three times the
+    # iterations that 1e-8 takes.
+    a, _ = W.problem(51, 0)
+    fam = W.source_family(n=51, count=2)
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    u = 2.0 ** -53
+    for s in range(2):
+        b = fam.rhs(s)[0]
+        nb = np.linalg.norm(b)
+        x8, i8 = oracle.pcg(a, b, tol=1e-8)
+        assert i8["status"] == oracle.CONVERGED and i8["iters"] < 400
+        r1, _ = oracle.residual(a, b, x8)
+        r2 = _residual_reversed_rows(a, b, x8)
+        assert np.linalg.norm(r1 - r2) / nb >= 1e-11
+        abs_ax = np.bincount(rows, weights=np.abs(a.val) * np.abs(x8[a.col]), minlength=a.n)
+        assert u * np.linalg.norm(abs_ax) / nb >= 5e-11
+        x, info = oracle.pcg(a, b, tol=1e-10, maxit=3 * i8["iters"])
+        assert info["status"] == oracle.MAXIT and info["replacements"] >= 2
+        assert info["relres_true"] > 1e-10

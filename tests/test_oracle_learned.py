@@ -81,5 +81,27 @@ def test_pod_modes():
     assert np.allclose(lam[:m], sv ** 2, rtol=1e-8, atol=1e-10 * sv[0] ** 2)
     resid = S - Phi @ (Phi.T @ S)
     assert abs(np.sum(resid ** 2) - np.sum(lam[k:])) <= 1e-8 * np.sum(lam)
-    C = pod.project(Phi, S)
-    assert np.allclose(pod.decode(Phi, C), Phi @ (Phi.T @ S))
+
+
+def test_pod_project_and_decode():
+    # For an orthonormal basis Q (from a QR factorisation): coefficients of a
+    # combination Q C are C; decoding the coefficients of a vector in the span
+    # returns it; unit coefficient vectors decode to the basis vectors, and a
+    # unit vector of R^N projects onto that row of the basis.
+    rng = np.random.default_rng(6)
+    N, k, m = 200, 7, 5
+    Q, _ = np.linalg.qr(rng.standard_normal((N, k)))
+    C = rng.standard_normal((k, m))
+    assert pod.project(Q, Q @ C).shape == (k, m)
+    assert np.max(np.abs(pod.project(Q, Q @ C) - C)) <= 1e-13
+    S = Q @ rng.standard_normal((k, m))
+    assert np.max(np.abs(pod.decode(Q, pod.project(Q, S)) - S)) <= 1e-13
+    assert np.array_equal(pod.decode(Q, np.eye(k)), Q)
+    for i in (0, 3, N - 1):
+        e = np.zeros((N, 1))
+        e[i] = 1.0
+        assert np.array_equal(pod.project(Q, e)[:, 0], Q[i])
+    # Orthogonal complement: a vector orthogonal to the span has zero coefficients.
+    v0 = rng.standard_normal(N)
+    v = v0 - Q @ (Q.T @ v0)
+    assert np.max(np.abs(pod.project(Q, v[:, None]))) <= 1e-13 * np.linalg.norm(v0)
