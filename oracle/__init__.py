@@ -11,6 +11,9 @@ Python binding never do, and this package never imports them.
   time the oracle on all host cores; its dot products sum in another order.
 - `mlp`: an FP64 numpy multilayer perceptron (forward, backward, Adam).
 - `pod`: proper orthogonal decomposition by the method of snapshots.
+- `block_cg`: block PCG for several right-hand sides (O'Leary's method in
+  the breakdown-free form, search blocks orthonormalised by shifted
+  Cholesky QR), numpy FP64 around the C oracle's product.
 """
 from __future__ import annotations
 
