@@ -54,11 +54,26 @@ def solve_bytes(n, nnz, iters, checks, form="standard", vb=8, ib=4):
 
 # HBM bytes per iteration from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a
 # 512 MiB copy: fetch x2, write x1) for the 51^3 system, keyed by form and
-# launch shape (nonzeros per lane, block size, column index bits).
-MEASURED_TRAFFIC = {
-    ("standard", 132651, 3442951, 16, 512, 16): 51.94e6,  # k_direction + k_update
-    ("single", 132651, 3442951, 16, 512, 16): 49.52e6,    # k_sr_iter
+# launch shape (nonzeros per lane, block size, column index bits).  Each entry
+# records the profile it came from and a hash of the kernel sources it was
+# measured on; once those sources change the figure no longer applies and the
+# roofline reports traffic as null.
+MEASURED_TRAFFIC = {}
+TRAFFIC_SOURCES = {
+    "standard": ("std_kernels.hpp", "tiles.hpp", "common.hpp"),
+    "single": ("sr_kernels.hpp", "tiles.hpp", "common.hpp"),
 }
+TRAFFIC_PROFILE = "profiles/pcg_iteration_kernels_51cube_hbm_counters.txt"
+
+
+def kernel_sources_sha(form):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[form]:
+        with open(os.path.join(ROOT, "paper_1107_0538_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def hbm_probe(dev, stream, mib=512, reps=20):
@@ -106,7 +121,9 @@ def roofline(form, n, nnz, run):
     per_iter_s = run["device_s"] / max(run["iters"], 1)
     ib = iter_bytes(n, nnz, form)
     launch = run["launch"]
-    traffic = MEASURED_TRAFFIC.get((form, n, nnz, launch["nnz_per_lane"], launch["block_size"], launch["col_bits"]))
+    entry = MEASURED_TRAFFIC.get((form, n, nnz, launch["nnz_per_lane"], launch["block_size"], launch["col_bits"]))
+    sha = kernel_sources_sha(form)
+    traffic = entry["bytes"] if entry and entry["sources_sha"] == sha else None
     # The stored format's compulsory bytes: 16-bit column offsets save 2 per
     # nonzero against the CSR count that `achieved` uses; the standard form's
     # whole {z, p} pair stores and loads add 24 per row, the single-reduction
@@ -116,21 +133,120 @@ def roofline(form, n, nnz, run):
         "kernel": ("k_sr_iter" if form == "single" else "k_direction + k_update") + " (one CG iteration)",
         "bound": "hbm", "achieved": ib / per_iter_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": ib / per_iter_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+        "traffic_source": TRAFFIC_PROFILE if traffic is not None else "kernel changed since the counters were taken",
+        "kernel_sources_sha": sha,
         "bytes_per_launch": ib, "launch_s": per_iter_s,
         "format_bytes_per_launch": fb, "format_frac": fb / per_iter_s / 1e9 / HBM_PEAK_GBS,
     }
 
 
-def cpu_model():
+def host_cpu():
+    """Model string, family/model numbers and core counts of the host."""
+    info = {"model_name": platform.processor() or "unknown"}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name":
+                    info["model_name"] = val
+                elif key in ("cpu family", "model", "stepping", "vendor_id") and key not in info:
+                    info[key.replace(" ", "_")] = val
+                if key == "" and "vendor_id" in info:
+                    break
     except OSError:
         pass
-    return platform.processor()
+    info["os_cpu_count"] = os.cpu_count()
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    return info
 
+
+def device_timed(stream, fn, reps):
+    """Mean device time of fn() over reps calls, from HIP events on `stream`."""
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def spmv_warm_cold(s, n, dev, stream, reps=200, cold_reps=20):
+    """Warm (back-to-back) and cold (2 GB written between) product times in seconds."""
+    import numpy as np
+    import torch
+
+    xv = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, n), device=dev)
+    yv = torch.empty_like(xv)
+    for _ in range(10):
+        s.spmv(xv, yv)
+    warm = device_timed(stream, lambda: s.spmv(xv, yv), reps)
+    flush = torch.empty(2 * 1024 ** 3 // 4, dtype=torch.float32, device=dev)
+    cold = []
+    for r in range(cold_reps):
+        flush.fill_(float(r))
+        cold.append(device_timed(stream, lambda: s.spmv(xv, yv), 1))
+    del flush
+    return warm, statistics.median(cold)
+
+
+_SYSTEMS = {}
+
+
+def system(n):
+    """The seed-0 problem on an n^3 grid, assembled once per run."""
+    import workloads as W
+
+    if n not in _SYSTEMS:
+        log(f"building {n}^3 system")
+        _SYSTEMS[n] = W.problem(n, 0)
+    return _SYSTEMS[n]
+
+
+def bench_hbm128(args, dev, stream):
+    """The HBM-bound figures: at 128^3 the matrix (677 MB) no longer fits the
+    256 MB last-level cache, so the product and the iteration stream from HBM."""
+    import torch
+
+    from paper_1107_0538_amd import Solver
+
+    a, b = system(128)
+    n, nnz = a.n, a.nnz
+    s = Solver(a)
+    cfg = s.config()
+    warm, cold = spmv_warm_cold(s, n, dev, stream, reps=50, cold_reps=10)
+    sb = spmv_bytes(n, nnz)
+    bt = torch.as_tensor(b, device=dev)
+    x = torch.zeros_like(bt)
+    s.cg_solve(bt, x)
+    infos = []
+    for _ in range(3):
+        x.zero_()
+        infos.append(s.cg_solve(bt, x))
+    it = infos[-1]
+    assert all(i["status"] == 0 for i in infos), it
+    per_iter = statistics.mean(i["seconds"] for i in infos) / it["iters"]
+    ib = iter_bytes(n, nnz, "standard")
+    out = {
+        "workload": f"q1hex 128^3 sigma+mass, N={n}, nnz={nnz}, FP64 Jacobi-PCG standard form, tol 1e-10",
+        "kernel": "k_direction + k_update (one CG iteration)", "bound": "hbm",
+        "achieved": ib / per_iter / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": ib / per_iter / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": ib, "launch_s": per_iter,
+        "iters": it["iters"], "relres_true": it["relres_true"],
+        "spmv": {"kernel": f"k_spmv<{cfg['spmv_nnz_per_lane']}, {cfg['spmv_block_size']}>", "bytes": sb,
+                 "warm_us": warm * 1e6, "warm_gbs": sb / warm / 1e9, "warm_frac": sb / warm / 1e9 / HBM_PEAK_GBS,
+                 "cold_us": cold * 1e6, "cold_gbs": sb / cold / 1e9, "cold_frac": sb / cold / 1e9 / HBM_PEAK_GBS},
+    }
+    log(f"128^3: {per_iter * 1e6:.1f} us/iter ({out['achieved']:.0f} GB/s), spmv warm {warm * 1e6:.1f} us, "
+        f"cold {cold * 1e6:.1f} us")
+    del s
+    return out
 
 
 def _timed(fn, reps):
@@ -157,11 +273,7 @@ def bench_mixed(args, a51, b51, s51):
 
     out = {}
     for n in (51, 128):
-        if n == 51:
-            a, b = a51, b51
-        else:
-            log("building 128^3 system")
-            a, b = W.problem(128, 0)
+        a, b = (a51, b51) if n == 51 else system(128)
         bt = torch.as_tensor(b, device="cuda")
         s64 = s51 if n == 51 else Solver(a)
         smx = Solver(a, fp32_copy=True)
@@ -235,8 +347,13 @@ def bench_batched(args, *_):
     diff = max(float(torch.linalg.vector_norm(x_cat[bt.offsets[k]:bt.offsets[k + 1]] - xs[k])
                      / torch.linalg.vector_norm(xs[k])) for k in range(256))
     teams, grid = bt.teams()
+    # Algorithmic bytes of the batched solve: every system's iterations at the
+    # FP64 iteration's byte count, plus its setup and final check.
+    abytes = sum(solve_bytes(m.n, m.nnz, i["iters"], 1 + i["replacements"]) for m, i in zip(mats, infos))
     out = {"systems": 256, "rows_total": bt.n_total, "nnz_total": int(sum(m.nnz for m in mats)),
            "batched_s": tb, "loop_s": tl, "speedup": tl / tb, "grid": grid,
+           "algorithmic_bytes": abytes, "achieved_gbs": abytes / tb / 1e9,
+           "frac_hbm_peak": abytes / tb / 1e9 / HBM_PEAK_GBS,
            "iters_min_max": [min(i["iters"] for i in infos), max(i["iters"] for i in infos)],
            "loop_iters_total": int(sum(i["iters"] for i in linfo)),
            "max_solution_relerr_vs_loop": diff}
@@ -271,6 +388,15 @@ def bench_multi(args, a, b, s):
             res.append(s.cg_solve(c, xv))
         return res
 
+    stream = torch.cuda.current_stream()
+    Y = torch.empty_like(Bd)
+    s.spmm(Bd, Y)
+    t_spmm = device_timed(stream, lambda: s.spmm(Bd, Y), 50)
+    mb = (12 * a.nnz + 4 * (a.n + 1) + 2 * 8 * a.n * 64)
+    spmm = {"s": 64, "us": t_spmm * 1e6, "bytes": mb, "gbs": mb / t_spmm / 1e9,
+            "frac_hbm_peak": mb / t_spmm / 1e9 / HBM_PEAK_GBS}
+    log(f"spmm 64 columns: {t_spmm * 1e6:.1f} us ({spmm['gbs']:.0f} GB/s)")
+    del Y
     fm()
     reps = max(3, min(args.steps, 5))
     tm, _, minfo = _timed(fm, reps)
@@ -291,7 +417,7 @@ def bench_multi(args, a, b, s):
     tx, _, xinfo = _timed(fmx, reps)
     assert all(i["status"] == 0 for i in xinfo)
     dx = max(float(torch.linalg.vector_norm(X32[:, j] - X[:, j]) / torch.linalg.vector_norm(X[:, j])) for j in range(64))
-    out = {"rhs": 64, "multi_s": tm, "loop_s": tl, "speedup": tl / tm,
+    out = {"rhs": 64, "spmm": spmm, "multi_s": tm, "loop_s": tl, "speedup": tl / tm,
            "multi_iters_max": max(i["iters"] for i in minfo), "loop_iters_max": max(i["iters"] for i in linfo),
            "max_solution_relerr_vs_loop": diff,
            "fp32_refine": {"s": tx, "speedup_vs_fp64_multi": tm / tx, "outer": xinfo[0]["outer"],
@@ -377,6 +503,7 @@ def main():
     ap.add_argument("--n", type=int, default=51, help="grid edge (51 = the paper's N and NNZ)")
     ap.add_argument("--spmv-reps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-hbm128", action="store_true", help="skip the 128^3 (HBM-bound) roofline record")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape by timing (default: the library's default shape, the one profiled)")
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
@@ -403,8 +530,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    log(f"building {args.n}^3 system")
-    a, b = W.problem(args.n, 0)
+    a, b = system(args.n)
     n, nnz = a.n, a.nnz
     s = Solver(a, autotune=args.autotune)
     cfg = s.config()
@@ -423,30 +549,10 @@ def main():
         del src, dst
 
     # --- SpMV bandwidth (warm: repeated products; cold: 2 GB written between products)
-    xv = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, n), device=dev)
-    yv = torch.empty_like(xv)
-    for _ in range(10):
-        s.spmv(xv, yv)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.spmv_reps):
-        s.spmv(xv, yv)
-    e1.record(stream)
-    e1.synchronize()
-    spmv_us = e0.elapsed_time(e1) * 1e3 / args.spmv_reps
-    flush = torch.empty(2 * 1024 ** 3 // 4, dtype=torch.float32, device=dev)
-    cold = []
-    for r in range(20):
-        flush.fill_(float(r))
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        c0.record(stream)
-        s.spmv(xv, yv)
-        c1.record(stream)
-        c1.synchronize()
-        cold.append(c0.elapsed_time(c1) * 1e3)
-    del flush
+    warm_s, cold_s = spmv_warm_cold(s, n, dev, stream, reps=args.spmv_reps)
+    spmv_us, cold_us = warm_s * 1e6, cold_s * 1e6
     sb = spmv_bytes(n, nnz)
-    log(f"spmv {spmv_us:.2f} us warm ({sb / spmv_us / 1e3:.0f} GB/s), cold median {statistics.median(cold):.2f} us")
+    log(f"spmv {spmv_us:.2f} us warm ({sb / spmv_us / 1e3:.0f} GB/s), cold median {cold_us:.2f} us")
 
     # --- achievable HBM bandwidth: the library's STREAM triad on 3 x 512 MiB
     probe = hbm_probe(dev, stream)
@@ -515,13 +621,17 @@ def main():
         "gflops_paper_convention": flops_iter * it["iters"] / wall / 1e9,
         "spmv": {
             "us": spmv_us, "gbs": sb / spmv_us / 1e3, "frac_hbm_peak": sb / spmv_us / 1e3 / HBM_PEAK_GBS,
-            "cold_us_median": statistics.median(cold), "cold_gbs": sb / statistics.median(cold) / 1e3,
+            "cold_us_median": cold_us, "cold_gbs": sb / cold_us / 1e3,
             "bytes": sb, "format_bytes": sb - (2 * nnz if cfg["col_bits"] == 16 else 0),
             "kernel": f"k_spmv<{cfg['spmv_nnz_per_lane']}, {cfg['spmv_block_size']}>",
             "nnz_per_lane": cfg["spmv_nnz_per_lane"], "block_size": cfg["spmv_block_size"], "grid": cfg["spmv_grid"],
         },
         "roofline": dict(roofline(best, n, nnz, r), achievable=probe["gbs"],
-                         frac_of_achievable=roofline(best, n, nnz, r)["achieved"] / probe["gbs"]),
+                         frac_of_achievable=roofline(best, n, nnz, r)["achieved"] / probe["gbs"],
+                         cache_resident=(f"the {args.n}^3 working set ({(iter_bytes(n, nnz, best)) / 1e6:.0f} MB) "
+                                         "fits the 256 MB last-level cache (MALL), so warm iterations are served "
+                                         "partly from it; roofline_128 is the HBM-bound figure")
+                         if iter_bytes(n, nnz, best) < 256e6 else None),
         "hbm_probe": probe,
         "paper_context": {"opencl_1gpu_tesla_t10_s": 0.659, "matlab_core2duo_s": 3.17,
                           "note": "different (unavailable) matrix and hardware; context only"},
@@ -530,24 +640,43 @@ def main():
     if not args.no_cpu:
         import oracle
 
-        # A bounded sample: whole oracle solves until about 12 s of CPU work.
-        ts = []
-        while len(ts) < 2 or (sum(ts) < 12.0 and len(ts) < 50):
-            t = time.perf_counter()
-            xo, io = oracle.pcg(a, b, tol=1e-10)
-            ts.append(time.perf_counter() - t)
-            if ts[-1] > 5.0:
-                log(f"cpu baseline: oracle solve {len(ts)} took {ts[-1]:.1f} s")
-        reps = len(ts)
-        log(f"cpu baseline: {reps} oracle solves, {sum(ts):.1f} s")
+        def sample(parallel, budget):
+            # A bounded sample: whole oracle solves until about `budget` s of CPU time.
+            ts = []
+            while len(ts) < 2 or (sum(ts) < budget and len(ts) < 50):
+                t = time.perf_counter()
+                xo, io = oracle.pcg(a, b, tol=1e-10, parallel=parallel)
+                ts.append(time.perf_counter() - t)
+                if ts[-1] > 5.0:
+                    log(f"cpu baseline: oracle solve {len(ts)} took {ts[-1]:.1f} s")
+            return ts, xo, io
+
+        cpu = host_cpu()
+        ts1, xo, io = sample(False, 8.0)
+        nthreads = oracle.threads(parallel=True)
+        tsp, xp, iop = sample(True, 6.0)
+        log(f"cpu baseline: {len(ts1)} single-thread solves {sum(ts1):.1f} s; {len(tsp)} solves on {nthreads} "
+            f"threads {sum(tsp):.1f} s")
         out["cpu_baseline"] = {
-            "value": statistics.mean(ts), "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full FP64 Jacobi-PCG solves of the same {args.n}^3 system "
-                      f"({io['iters']} iterations each), single-threaded C, {cpu_model()}",
-            "iters": io["iters"],
+            "value": statistics.mean(tsp), "unit": "s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{len(tsp)} full FP64 Jacobi-PCG solves of the same {args.n}^3 system "
+                      f"({iop['iters']} iterations each), the oracle's C source built with OpenMP, "
+                      f"{nthreads} threads on {cpu['model_name']}",
+            "iters": iop["iters"], "host": cpu,
+            "single_thread": {"value": statistics.mean(ts1), "unit": "s", "cores": 1, "solves": len(ts1),
+                              "iters": io["iters"]},
         }
         out["gpu_vs_oracle_solution_relerr"] = {
             f: float(np.linalg.norm(runs[f]["x"] - xo) / np.linalg.norm(xo)) for f in runs}
+        dxo = xo - xo.mean()
+        out["gpu_vs_oracle_solution_relerr_mean_removed"] = {
+            f: float(np.linalg.norm((runs[f]["x"] - runs[f]["x"].mean()) - dxo) / np.linalg.norm(dxo)) for f in runs}
+    if not args.no_hbm128:
+        try:
+            out["roofline_128"] = bench_hbm128(args, dev, stream)
+        except Exception as e:
+            log(f"128^3 roofline failed: {e!r}")
+            out["roofline_128"] = {"error": repr(e)}
     forms = [f for f in args.forms.split(",") if f]
     if forms:
         out["forms_vs_fp64"] = {}
