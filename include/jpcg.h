@@ -216,6 +216,33 @@ int cg_solve_multi_mixed(cg_ctx *ctx, const double *B, double *X, int32_t s, dou
                          double tol_inner, int32_t maxit_inner, cg_info *info);
 
 /*
+ * Block conjugate gradients for s right-hand sides at once: O'Leary's block
+ * method (the paper's CG iteration, Section IV, applied to a block of
+ * vectors) in the breakdown-free form of Ji and Li.  Each iteration makes one
+ * block product Q = A P of the N x s search block, takes s x s matrices
+ * alpha = (P'Q)^-1 P'R and beta = -(P'Q)^-1 Q'Z in place of CG's scalars, and
+ * orthonormalises the next search block Z + P beta by three CholeskyQR passes
+ * (the first shifted, as Fukaya, Kannan, Nakatsukasa, Zhang and Yamamoto
+ * describe; columns scaled to unit norm; columns whose pivot after the
+ * shifted pass is <= 1e-14 are dropped as dependent).  The Krylov space grows
+ * by up to s directions per iteration, so the columns need fewer iterations
+ * than s separate solves; the iterates differ from cg_solve's by design.
+ * B and X: device, row-major n x s (leading dimension s), 1 <= s <= 64; X
+ * holds X0 on input and the solution on output; B and X must not alias.
+ * Stops when every column passes ||b_j - A x_j|| <= tol ||b_j||, tested on
+ * the recurrence residuals and confirmed on the true residuals; if a column
+ * fails the confirmation the block restarts from the true residuals.
+ * maxit <= 0 means n (counted in block products).  info (s entries): iters =
+ * block iterations (the same for every column), status, replacements =
+ * restarts, outer = rank of the last search block, relres_recur, relres_true
+ * (of the returned x_j), seconds.  Columns with b_j = 0 return x_j = 0.
+ * Synchronous.  Returns CG_CONVERGED, CG_MAXIT, CG_BREAKDOWN (P'AP not
+ * positive definite on the live directions, or a non-finite value), or an
+ * API error.
+ */
+int cg_solve_block(cg_ctx *ctx, const double *B, double *X, int32_t s, double tol, int32_t maxit, cg_info *info);
+
+/*
  * Batched solves: nsys independent SPD systems solved together in one
  * persistent kernel launch (captured in a hipGraph).  systems[s] must be in
  * host memory (mem = CG_MEM_HOST) and is validated like cg_create's input;

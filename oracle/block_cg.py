@@ -29,13 +29,12 @@ Yamamoto (SIAM J. Sci. Comput. 42, 2020): CholeskyQR with a shift of
 more, which gives an orthonormal basis for condition numbers up to ~1/u
 (these blocks reach 1e9, beyond plain or repeated CholeskyQR).  Here the
 columns are scaled to unit norm first (so the decisions do not depend on the
-columns' scales), every Cholesky factorisation is pivoted (largest remaining
-diagonal first), and the second and third factorisations stop at the first
-pivot <= tau: a direction whose remaining pivot is that small after the
+columns' scales), and the second and third factorisations drop every column
+whose pivot is <= tau: a direction whose remaining pivot is that small after the
 first, shifted pass is dependent on the ones already taken.  Each pass forms
-its block explicitly (W_k = W_{k-1} T_k, T_k the inverse transposed factor
-placed by the pivot order), as the method requires; columns of P beyond the
-rank r are zero.
+its block explicitly (W_k = W_{k-1} T_k, T_k the inverse transposed factor),
+as the method requires.  Kept columns stay in place and dropped ones become
+zero columns; the live columns of P form the basis.
 
 Iterations count block products A P in the loop (as in the single-vector
 oracle).  Statuses: CONVERGED, MAXIT, BREAKDOWN (P'Q not positive definite,
@@ -57,46 +56,50 @@ def spmm(a, X):
     return np.stack([spmv(a, np.ascontiguousarray(X[:, j])) for j in range(X.shape[1])], axis=1)
 
 
-def pivoted_cholesky(G, tau):
-    """Pivoted Cholesky of a symmetric PSD matrix G (s x s).
+def cholesky_drop(G, tau):
+    """Cholesky factorisation of a symmetric PSD matrix G (s x s) that drops
+    dependent columns.
 
-    At step k the largest remaining diagonal entry (lowest index on ties) is
-    moved to position k; the factorisation stops before the first pivot that
-    is not > tau.  Returns (perm, L, r): G[perm[:r]][:, perm[:r]] = L L' with
-    L lower triangular (r x r) and perm a permutation of range(s).
+    Columns are taken in order; column k's pivot is its remaining diagonal
+    entry after the kept columns before it (the squared distance of column k
+    from their span, for a Gram matrix).  A pivot <= tau drops column k:
+    its column of L is zero and it takes no part in later updates.  Returns
+    (L, keep): L lower triangular with G[keep][:, keep] = L_kk L_kk', where
+    L_kk is L restricted to the kept rows and columns.
     """
     s = G.shape[0]
     A = np.array(G, dtype=np.float64, copy=True)
-    perm = np.arange(s)
-    r = s
+    L = np.zeros((s, s))
+    keep = np.zeros(s, dtype=bool)
     for k in range(s):
-        j = k + int(np.argmax(np.diag(A)[k:]))
-        if not (A[j, j] > tau):
-            r = k
-            break
-        A[[k, j]] = A[[j, k]]
-        A[:, [k, j]] = A[:, [j, k]]
-        perm[[k, j]] = perm[[j, k]]
-        A[k, k] = np.sqrt(A[k, k])
-        A[k + 1:, k] = A[k + 1:, k] / A[k, k]
-        A[k + 1:, k + 1:] -= np.outer(A[k + 1:, k], A[k + 1:, k])
-    return perm, np.tril(A[:r, :r]), r
+        d = A[k, k]
+        if not (d > tau):
+            continue
+        keep[k] = True
+        L[k, k] = np.sqrt(d)
+        L[k + 1:, k] = A[k + 1:, k] / L[k, k]
+        A[k + 1:, k + 1:] -= np.outer(L[k + 1:, k], L[k + 1:, k])
+    return L, keep
 
 
-def _factor_to_t(perm, L, r, s):
-    """T (s x s) with W T = W[:, perm[:r]] L^-T in columns 0..r-1, zero after."""
+def _inverse_factor(L, keep):
+    """T (s x s) = L_kk^-T placed at the kept rows and columns, zero elsewhere:
+    W T holds W[:, keep] L_kk^-T in the kept columns and zero in the others."""
+    s = L.shape[0]
     T = np.zeros((s, s))
-    if r:
-        T[perm[:r], :r] = np.linalg.solve(L, np.eye(r)).T
+    idx = np.flatnonzero(keep)
+    if idx.size:
+        T[np.ix_(idx, idx)] = np.linalg.solve(L[np.ix_(idx, idx)], np.eye(idx.size)).T
     return T
 
 
 def orth(W, tau=TAU):
-    """(P, r): an orthonormal basis of the numerical column span of W (N x s).
+    """(P, keep): an orthonormal basis of the numerical column span of W (N x s),
+    in the kept columns of P (the others are zero).
 
-    Three CholeskyQR passes, each W_k = W_{k-1} T_k with T_k from the pivoted
+    Three CholeskyQR passes, each W_k = W_{k-1} T_k with T_k from the
     Cholesky factor of the Gram matrix of W_{k-1}; the first on the
-    column-scaled W with the shift, the other two with the rank cut-off tau.
+    column-scaled W with the shift, the other two dropping columns at tau.
     """
     W = np.asarray(W, dtype=np.float64)
     n, s = W.shape
@@ -105,26 +108,27 @@ def orth(W, tau=TAU):
     W0 = W * D
     G = W0.T @ W0
     shift = 11.0 * (n * s + s * (s + 1)) * UNIT_ROUNDOFF * np.trace(G)
-    perm, L, r = pivoted_cholesky(G + shift * np.eye(s), 0.0)
-    Wk = W0 @ _factor_to_t(perm, L, r, s)
+    L, keep = cholesky_drop(G + shift * np.eye(s), 0.0)
+    Wk = W0 @ _inverse_factor(L, keep)
     for _ in range(2):
-        perm, L, r = pivoted_cholesky(Wk.T @ Wk, tau)
-        Wk = Wk @ _factor_to_t(perm, L, r, s)
-    return Wk, r
+        L, keep = cholesky_drop(Wk.T @ Wk, tau)
+        Wk = Wk @ _inverse_factor(L, keep)
+    return Wk, keep
 
 
-def _spd_solve(C_full, r, rhs):
-    """Rows 0..r-1 of Gamma^-1 rhs for Gamma = C_full[:r, :r] (Cholesky), zero rows after; None if not SPD."""
+def _spd_solve(gamma, live, rhs):
+    """gamma[live][:, live]^-1 rhs[live] at the live rows, zero rows elsewhere
+    (Cholesky); None if that block is not positive definite."""
     out = np.zeros_like(rhs)
-    if r == 0:
+    idx = np.flatnonzero(live)
+    if idx.size == 0:
         return out
-    G = C_full[:r, :r]
+    G = gamma[np.ix_(idx, idx)]
     try:
         C = np.linalg.cholesky(0.5 * (G + G.T))
     except np.linalg.LinAlgError:
         return None
-    y = np.linalg.solve(C, rhs[:r])
-    out[:r] = np.linalg.solve(C.T, y)
+    out[idx] = np.linalg.solve(C.T, np.linalg.solve(C, rhs[idx]))
     return out
 
 
@@ -170,14 +174,14 @@ def block_pcg(a, B, X0=None, tol=1e-10, maxit=0, precond="jacobi", tau=TAU, hist
     if not np.all(np.isfinite(R)):
         return finish(BREAKDOWN, 0, 0, [], hist)
     Z = dinv[:, None] * R
-    P, r = orth(Z, tau)
-    ranks = [r]
+    P, live = orth(Z, tau)
+    ranks = [int(live.sum())]
     k = repl = 0
     status = MAXIT
     while k < maxit:
         Q = spmm(a, P)
         PQ = P.T @ Q
-        alpha = _spd_solve(PQ, r, P.T @ R)
+        alpha = _spd_solve(PQ, live, P.T @ R)
         if alpha is None or not np.all(np.isfinite(alpha)):
             status = BREAKDOWN
             break
@@ -196,18 +200,18 @@ def block_pcg(a, B, X0=None, tol=1e-10, maxit=0, precond="jacobi", tau=TAU, hist
             R = Rt
             repl += 1
             Z = dinv[:, None] * R
-            P, r = orth(Z, tau)
-            ranks.append(r)
+            P, live = orth(Z, tau)
+            ranks.append(int(live.sum()))
             continue
         Z = dinv[:, None] * R
-        beta = _spd_solve(PQ, r, Q.T @ Z)
+        beta = _spd_solve(PQ, live, Q.T @ Z)
         if beta is None:
             status = BREAKDOWN
             break
         beta = -beta
-        P, r = orth(Z + P @ beta, tau)
-        ranks.append(r)
-        if r == 0:
+        P, live = orth(Z + P @ beta, tau)
+        ranks.append(int(live.sum()))
+        if not live.any():
             status = BREAKDOWN
             break
     return finish(status, k, repl, ranks, hist)

@@ -71,6 +71,8 @@ SIGNATURES = {
                                       ctypes.POINTER(cg_info)]),
     "cg_solve_multi_mixed": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                             ctypes.c_double, ctypes.c_int32, ctypes.POINTER(cg_info)]),
+    "cg_solve_block": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.POINTER(cg_info)]),
     "cg_batch_create": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(cg_opts), _P, ctypes.POINTER(_P)]),
     "cg_batch_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(cg_info)]),
     "cg_batch_offset": (ctypes.c_int64, [_P, ctypes.c_int32]),

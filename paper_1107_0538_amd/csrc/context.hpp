@@ -48,6 +48,7 @@ struct cg_ctx {
     struct cg_spmv_plan* spmv = nullptr;     // the standalone product's tiling and grid
     struct cg_multi* multi = nullptr;        // multi-RHS solver for one block width
     struct cg_multi* multi32 = nullptr;      // FP32 multi-RHS inner solver (mixed form)
+    struct cg_block* block = nullptr;        // block CG solver (up to 64 right-hand sides)
     double* hist = nullptr;
     int hist_cap = 0;
     int hist_len = 0;
@@ -78,5 +79,8 @@ int set_error(cg_ctx* c, int code, const std::string& msg);
 
 // Free the multi-RHS solver state of a context (multi.hip).
 void free_multi(cg_ctx* c);
+
+// Free the block solver state of a context (block.hip).
+void free_block(cg_ctx* c);
 
 }  // namespace jpcg

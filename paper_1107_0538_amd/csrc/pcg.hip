@@ -850,6 +850,7 @@ static void free_ctx(cg_ctx* c)
     destroy_graphs(c->graphs32);
     destroy_spmv_plan(c->spmv);
     free_multi(c);
+    free_block(c);
     if (c->mixed_dev) (void)hipFree(c->mixed_dev);
     if (c->mixed_host) (void)hipHostFree(c->mixed_host);
     void* ptrs[] = {c->rowptr, c->col, c->val, c->dinv, c->val32, c->dinv32, c->rowsum32, c->work[0], c->hist};

@@ -184,6 +184,22 @@ class Solver:
         infos = self.cg_solve_multi(B, X, tol, maxit)
         return X, infos
 
+    def cg_solve_block(self, B, X, tol=1e-10, maxit=0) -> list:
+        """Block CG over the n x s block B (one shared Krylov space); X holds X0 and the solution."""
+        self._as_block(B, "B")
+        self._as_block(X, "X")
+        s = B.shape[1]
+        infos = (capi.cg_info * s)()
+        rc = self._lib.cg_solve_block(self.ctx, B.data_ptr(), X.data_ptr(), s, float(tol), int(maxit), infos)
+        capi.check(rc, self.ctx)
+        return [infos[j].as_dict() for j in range(s)]
+
+    def solve_block(self, B, X0=None, tol=1e-10, maxit=0):
+        torch = _torch()
+        X = torch.zeros_like(B) if X0 is None else X0.clone()
+        infos = self.cg_solve_block(B, X, tol, maxit)
+        return X, infos
+
     def cg_solve_multi_mixed(self, B, X, tol=1e-10, maxit_outer=0, tol_inner=0.0, maxit_inner=0) -> list:
         self._as_block(B, "B")
         self._as_block(X, "X")

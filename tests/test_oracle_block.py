@@ -39,22 +39,30 @@ def spd(n, cond, seed):
     return (Q * lam) @ Q.T
 
 
-def test_pivoted_cholesky_factors_the_matrix():
+def test_cholesky_drop_factors_the_kept_columns():
     rng = np.random.default_rng(0)
     for s, rank in [(6, 6), (9, 4), (64, 64), (64, 17)]:
         F = rng.standard_normal((s, rank)) * np.geomspace(1.0, 1e-3, rank)
         G = F @ F.T
-        perm, L, r = bc.pivoted_cholesky(G, 1e-12 * np.max(np.diag(G)))
-        assert r == rank
-        assert sorted(perm.tolist()) == list(range(s))
-        Gp = G[np.ix_(perm[:r], perm[:r])]
-        assert np.max(np.abs(L @ L.T - Gp)) <= 1e-12 * np.max(np.abs(G))
+        L, keep = bc.cholesky_drop(G, 1e-12 * np.max(np.diag(G)))
+        assert int(keep.sum()) == rank
+        idx = np.flatnonzero(keep)
+        Lk = L[np.ix_(idx, idx)]
+        assert np.max(np.abs(Lk @ Lk.T - G[np.ix_(idx, idx)])) <= 1e-12 * np.max(np.abs(G))
         assert np.allclose(L, np.tril(L))
-        # Complete pivoting: the pivots never increase.
-        piv = np.diag(L) ** 2
-        assert np.all(np.diff(piv) <= 1e-12 * piv[0])
-        # The first pivot is the largest diagonal entry.
-        assert perm[0] == int(np.argmax(np.diag(G)))
+        assert not L[:, ~keep].any()
+        # Columns are taken greedily in order: the first `rank` columns of a
+        # random rank-`rank` Gram matrix are independent, the rest dependent.
+        assert np.array_equal(idx, np.arange(rank))
+    # A zero column and a repeated column are dropped where they occur.
+    F = rng.standard_normal((5, 8))
+    Wm = np.concatenate([F[:, :2], np.zeros((5, 1)), F[:, :1], F[:, 2:4]], axis=1)
+    L, keep = bc.cholesky_drop(Wm.T @ Wm, 1e-12)
+    assert keep.tolist() == [True, True, False, False, True, True]
+    # The matrix of a full-rank Gram factorisation is the textbook Cholesky factor.
+    G = F.T @ F + np.eye(8)
+    L, keep = bc.cholesky_drop(G, 0.0)
+    assert keep.all() and np.allclose(L, np.linalg.cholesky(G), rtol=1e-13, atol=1e-13)
 
 
 def test_orth_ill_conditioned_and_rank_deficient():
@@ -64,26 +72,26 @@ def test_orth_ill_conditioned_and_rank_deficient():
     V, _ = np.linalg.qr(rng.standard_normal((s, s)))
     for cond in (1e2, 1e9, 1e12):
         Wm = (U * np.geomspace(1.0, 1.0 / cond, s)) @ V.T * 7.0
-        P, r = bc.orth(Wm)
-        assert r == s
+        P, keep = bc.orth(Wm)
+        assert keep.all()
         assert np.max(np.abs(P.T @ P - np.eye(s))) <= 1e-12
         # Same span: W is reproduced from its coefficients in P.
         assert np.linalg.norm(Wm - P @ (P.T @ Wm)) <= 1e-10 * np.linalg.norm(Wm)
     # Rank 5: 11 columns are combinations of the first 5; one zero column.
     F = rng.standard_normal((n, 5))
     Wm = np.concatenate([F, F @ rng.standard_normal((5, 10)), np.zeros((n, 1))], axis=1)
-    P, r = bc.orth(Wm)
-    assert r == 5
-    assert np.max(np.abs(P[:, :r].T @ P[:, :r] - np.eye(r))) <= 1e-12
-    assert not P[:, r:].any()
+    P, keep = bc.orth(Wm)
+    assert keep.tolist() == [True] * 5 + [False] * 11
+    assert np.max(np.abs(P[:, keep].T @ P[:, keep] - np.eye(5))) <= 1e-12
+    assert not P[:, ~keep].any()
     assert np.linalg.norm(Wm - P @ (P.T @ Wm)) <= 1e-10 * np.linalg.norm(Wm)
     # Column scales do not change the decision: an independent direction held
     # only by a column 1e-18 times smaller than the others is kept.
-    P2, r2 = bc.orth(Wm * np.geomspace(1e-8, 1e8, Wm.shape[1]))
-    assert r2 == 5
+    P2, keep2 = bc.orth(Wm * np.geomspace(1e-8, 1e8, Wm.shape[1]))
+    assert int(keep2.sum()) == 5
     g = rng.standard_normal((n, 1))
-    P3, r3 = bc.orth(np.concatenate([F * 1e8, g * 1e-10], axis=1))
-    assert r3 == 6
+    P3, keep3 = bc.orth(np.concatenate([F * 1e8, g * 1e-10], axis=1))
+    assert keep3.all()
     assert np.linalg.norm(g - P3 @ (P3.T @ g)) <= 1e-10 * np.linalg.norm(g)
 
 

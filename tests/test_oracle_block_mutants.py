@@ -19,20 +19,21 @@ MUTANTS = {
     "x_update_sign": ("        X += P @ alpha\n", "        X -= P @ alpha\n"),
     "residual_uses_p": ("        R -= Q @ alpha\n", "        R -= P @ alpha\n"),
     "beta_sign": ("        beta = -beta\n", ""),
-    "beta_wrong_operand": ("beta = _spd_solve(PQ, r, Q.T @ Z)", "beta = _spd_solve(PQ, r, P.T @ Z)"),
-    "alpha_wrong_operand": ("alpha = _spd_solve(PQ, r, P.T @ R)", "alpha = _spd_solve(PQ, r, Q.T @ R)"),
+    "beta_wrong_operand": ("beta = _spd_solve(PQ, live, Q.T @ Z)", "beta = _spd_solve(PQ, live, P.T @ Z)"),
+    "alpha_wrong_operand": ("alpha = _spd_solve(PQ, live, P.T @ R)", "alpha = _spd_solve(PQ, live, Q.T @ R)"),
     "jacobi_multiplies": ("        dinv = 1.0 / d\n", "        dinv = d\n"),
-    "no_shift": ("pivoted_cholesky(G + shift * np.eye(s), 0.0)", "pivoted_cholesky(G, 0.0)"),
-    "one_cholqr_pass": ("    for _ in range(2):\n        perm, L, r = pivoted_cholesky(Wk.T @ Wk, tau)",
-                        "    for _ in range(0):\n        perm, L, r = pivoted_cholesky(Wk.T @ Wk, tau)"),
-    "factor_not_transposed": ("np.linalg.solve(L, np.eye(r)).T\n", "np.linalg.solve(L, np.eye(r))\n"),
-    "pivot_update_sign": ("A[k + 1:, k + 1:] -= np.outer", "A[k + 1:, k + 1:] += np.outer"),
-    "pivot_smallest_first": ("j = k + int(np.argmax(np.diag(A)[k:]))", "j = k + int(np.argmin(np.diag(A)[k:]))"),
+    "no_shift": ("cholesky_drop(G + shift * np.eye(s), 0.0)", "cholesky_drop(G, 0.0)"),
+    "one_cholqr_pass": ("    for _ in range(2):\n        L, keep = cholesky_drop(Wk.T @ Wk, tau)",
+                        "    for _ in range(0):\n        L, keep = cholesky_drop(Wk.T @ Wk, tau)"),
+    "factor_not_transposed": ("np.linalg.solve(L[np.ix_(idx, idx)], np.eye(idx.size)).T\n",
+                              "np.linalg.solve(L[np.ix_(idx, idx)], np.eye(idx.size))\n"),
+    "cholesky_update_sign": ("A[k + 1:, k + 1:] -= np.outer", "A[k + 1:, k + 1:] += np.outer"),
+    "cholesky_keeps_dependent": ("        if not (d > tau):\n            continue", "        if not (d > 0.0):\n            continue"),
     "no_column_scaling": ("    W0 = W * D\n", "    W0 = W\n"),
 }
 
 PINS = [
-    pins.test_pivoted_cholesky_factors_the_matrix,
+    pins.test_cholesky_drop_factors_the_kept_columns,
     pins.test_orth_ill_conditioned_and_rank_deficient,
     lambda: pins.test_one_column_is_the_single_vector_iteration("jacobi"),
     lambda: pins.test_matches_cholesky(40, 5, 1e4),
