@@ -5,14 +5,15 @@
 //
 // Per iteration, on N x 64 row-major FP64 blocks (columns >= s are zero):
 //   Q = A P                                  k_bc_spmm (row products, lane = column)
-//   Gamma = P'Q, Psi = P'R                   k_bc_gram<2> + k_bc_reduce
+//   Gamma = P'Q, Psi = P'R                   k_bc_gram<2> + k_bc_sum
 //   alpha = Gamma^-1 Psi                     k_bc_alpha (one workgroup: Cholesky over
 //                                            the live columns, inverse factor)
-//   X += P alpha, R -= Q alpha, Z = M^-1 R   k_bc_gemm<UPDATE> (+ column norms of R)
-//   Q'Z                                      k_bc_gram<1> + k_bc_reduce
+//   X += P alpha                             k_bc_gemm<XUP>
+//   R -= Q alpha, Z = M^-1 R, ||r_j||^2      k_bc_gemm<RUP> + k_bc_sum
+//   Q'Z                                      k_bc_gram<1> + k_bc_sum
 //   test, beta = -Gamma^-1 Q'Z               k_bc_beta
 //   W = Z + P beta                           k_bc_gemm<DIR>
-//   three CholeskyQR passes of W -> P        (k_bc_gram<1>, k_bc_reduce, k_bc_orth,
+//   three CholeskyQR passes of W -> P        (k_bc_gram<1>, k_bc_sum, k_bc_orth,
 //                                            k_bc_gemm<APPLY>) x 3
 // The Gram and block-times-64x64 products are dense contractions: they run on
 // the FP64 matrix cores (v_mfma_f64_16x16x4f64), operands straight from
@@ -76,7 +77,7 @@ __device__ __forceinline__ bool bc_stopped(const BcState* st, int gate)
 constexpr int kGramBS = 256;
 
 template <int NOP>
-__global__ __launch_bounds__(kGramBS) void k_bc_gram(int n, const double* __restrict__ U,
+__global__ __launch_bounds__(kGramBS, 2) void k_bc_gram(int n, const double* __restrict__ U,
                                                      const double* __restrict__ V0, const double* __restrict__ V1,
                                                      double* __restrict__ part, int rows_per_wg, int G,
                                                      const BcState* st, int gate)
@@ -95,20 +96,33 @@ __global__ __launch_bounds__(kGramBS) void k_bc_gram(int n, const double* __rest
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = d4{0.0, 0.0, 0.0, 0.0};
     const int rq = lane >> 4, cq = lane & 15;
-    for (int r0 = rs + 4 * sub; r0 < re; r0 += 4 * kWavesPerOp) {
+    // The loads of the next 4-row step are issued before this step's products.
+    double a[4], b[4];
+    auto fetch = [&](int r0) {
         const int row = r0 + rq;
         const bool ok = row < re;
         const size_t o = (size_t)(ok ? row : rs) * kB + cq;
-        double a[4], b[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             a[q] = ok ? U[o + 16 * q] : 0.0;
             b[q] = ok ? V[o + 16 * q] : 0.0;
         }
+    };
+    int r0 = rs + 4 * sub;
+    if (r0 < re) fetch(r0);
+    while (r0 < re) {
+        double ca[4], cb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ca[q] = a[q];
+            cb[q] = b[q];
+        }
+        r0 += 4 * kWavesPerOp;
+        if (r0 < re) fetch(r0);
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-            for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ib], b[jb], acc[ib][jb], 0, 0, 0);
+            for (int jb = 0; jb < 4; ++jb) acc[ib][jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[ib], cb[jb], acc[ib][jb], 0, 0, 0);
     }
     // Add the waves of each operand in wave order.
     for (int t = 0; t < kWavesPerOp; ++t) {
@@ -130,52 +144,71 @@ __global__ __launch_bounds__(kGramBS) void k_bc_gram(int n, const double* __rest
     for (int e = threadIdx.x; e < NOP * kBB; e += kGramBS) out[e] = red[e / kBB][e % kBB];
 }
 
-// dst_o[e] = sum over workgroups g (in order) of part[g][o][e].
-__global__ __launch_bounds__(256) void k_bc_reduce(const double* __restrict__ part, int G, int nop,
-                                                   BcState* st, int gate)
+// dst[e] = sum over g of part[g * count + e] for e < count, in a fixed order:
+// a workgroup takes EPB consecutive entries; its 256 / EPB thread groups add
+// the partials g = q, q + groups, ... (group q), and the group sums are added
+// in group order.  which 0: Gram partials, entries [0, 4096) to st->G0 and
+// [4096, 8192) to st->G1; which 1: column norms to st->rr.
+template <int EPB>
+__global__ __launch_bounds__(256) void k_bc_sum(const double* __restrict__ part, int G, int count, int which,
+                                                BcState* st, int gate)
 {
     if (bc_stopped(st, gate)) return;
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= nop * kBB) return;
-    const int o = e / kBB, i = e % kBB;
+    constexpr int kGroups = 256 / EPB;
+    __shared__ double red[kGroups][EPB];
+    const int j = threadIdx.x % EPB, q = threadIdx.x / EPB;
+    const int e = blockIdx.x * EPB + j;
     double s = 0.0;
-    for (int g = 0; g < G; ++g) s += part[((size_t)g * nop + o) * kBB + i];
-    (o == 0 ? st->G0 : st->G1)[i] = s;
+    if (e < count) {
+        int g = q;
+        for (; g + 3 * kGroups < G; g += 4 * kGroups) {
+            const double a0 = part[(size_t)g * count + e], a1 = part[(size_t)(g + kGroups) * count + e];
+            const double a2 = part[(size_t)(g + 2 * kGroups) * count + e], a3 = part[(size_t)(g + 3 * kGroups) * count + e];
+            s += (a0 + a1) + (a2 + a3);
+        }
+        for (; g < G; g += kGroups) s += part[(size_t)g * count + e];
+    }
+    red[q][j] = s;
+    __syncthreads();
+    if (q == 0 && e < count) {
+        double t = 0.0;
+        for (int k = 0; k < kGroups; ++k) t += red[k][j];
+        if (which == 0) (e < kBB ? st->G0[e] : st->G1[e - kBB]) = t;
+        else st->rr[e] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Block times 64 x 64: Y = U M with U N x 64 and M = st->M.  Per wave a tile
-// of 16 rows: D (16 x 64) = sum over 16 steps t of A_t B_t with the reduction
+// Block times 64 x 64: U M with U N x 64 and M = st->M.  Per wave a tile of
+// 16 rows: D (16 x 64) = sum over 16 steps t of A_t B_t with the reduction
 // index permuted so that lane l's A values are 16 contiguous entries of one
 // row: step t, lane l holds A = U[r0 + l % 16][16 (l / 16) + t] and
 // B = M[16 (l / 16) + t][16 jb + l % 16] (read from LDS).
-//   BC_UPDATE: X += P M, R -= Q M, Z = M^-1 R, per-column partials of r'r
-//   BC_DIR:    W = Z + P M
-//   BC_APPLY:  Y = U M
+//   BC_XUP:   Y += U M                     (X += P alpha)
+//   BC_RUP:   Y -= U M, Z = M^-1 Y, per-column partials of y'y
+//                                          (R -= Q alpha, Z, ||r_j||^2)
+//   BC_DIR:   Y = Z + U M                  (W = Z + P beta)
+//   BC_APPLY: Y = U M
 // ---------------------------------------------------------------------------
-enum BcGemm : int { BC_UPDATE = 0, BC_DIR = 1, BC_APPLY = 2 };
+enum BcGemm : int { BC_XUP = 0, BC_RUP = 1, BC_DIR = 2, BC_APPLY = 3 };
 constexpr int kGemmBS = 256;
 constexpr int kMPad = 65;  // LDS row pitch of M (doubles)
 
 struct BcGemmArgs {
     int n;
-    const double* U;   // P (UPDATE, DIR) or the block to transform (APPLY)
-    const double* U2;  // Q (UPDATE)
-    double* Y;         // X (UPDATE), W (DIR), output (APPLY)
-    double* Y2;        // R (UPDATE)
-    const double* Z;   // Z (DIR) / Z output (UPDATE)
+    const double* U;
+    double* Y;
+    double* Z;          // BC_RUP: written; BC_DIR: read
     const double* dinv;
-    double* part;      // UPDATE: [G][64] partials of r'r
+    double* part;       // BC_RUP: [G][64] partials of y'y
     int G;
 };
 
-__device__ __forceinline__ void bc_tile_product(const double* __restrict__ U, int r0, int n, const double* Ms,
-                                                d4 (&acc)[4])
+__device__ __forceinline__ void bc_tile_load(const double* __restrict__ U, int r0, int n, double (&a)[16])
 {
     const int lane = threadIdx.x & 63, rq = lane >> 4, cq = lane & 15;
     const int row = r0 + cq;
     const bool ok = row < n;
-    double a[16];
     const double2* src = (const double2*)(U + (size_t)(ok ? row : 0) * kB + 16 * rq);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -183,6 +216,11 @@ __device__ __forceinline__ void bc_tile_product(const double* __restrict__ U, in
         a[2 * t] = v.x;
         a[2 * t + 1] = v.y;
     }
+}
+
+__device__ __forceinline__ void bc_tile_product(const double (&a)[16], const double* Ms, d4 (&acc)[4])
+{
+    const int lane = threadIdx.x & 63, rq = lane >> 4, cq = lane & 15;
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) acc[jb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -193,7 +231,7 @@ __device__ __forceinline__ void bc_tile_product(const double* __restrict__ U, in
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kGemmBS) void k_bc_gemm(BcGemmArgs g, BcState* st, int gate)
+__global__ __launch_bounds__(kGemmBS, 2) void k_bc_gemm(BcGemmArgs g, BcState* st, int gate)
 {
     if (bc_stopped(st, gate)) return;
     __shared__ double Ms[kB * kMPad];
@@ -206,43 +244,45 @@ __global__ __launch_bounds__(kGemmBS) void k_bc_gemm(BcGemmArgs g, BcState* st, 
     const int tpw = (tiles + g.G - 1) / g.G;
     const int t0 = min(L * tpw, tiles), t1 = min(t0 + tpw, tiles);
     double nrm[4] = {0.0, 0.0, 0.0, 0.0};
-    if (MODE == BC_UPDATE && L == 0 && threadIdx.x == 0) st->k += 1;
-    for (int tile = t0 + w; tile < t1; tile += kGemmBS / 64) {
+    if (MODE == BC_XUP && L == 0 && threadIdx.x == 0) st->k += 1;
+    // The next tile's row loads are issued before this tile's products.
+    double a[16];
+    int tile = t0 + w;
+    if (tile < t1) bc_tile_load(g.U, tile * 16, g.n, a);
+    while (tile < t1) {
         const int r0 = tile * 16;
+        double ca[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) ca[u] = a[u];
+        tile += kGemmBS / 64;
+        if (tile < t1) bc_tile_load(g.U, tile * 16, g.n, a);
         d4 acc[4];
-        bc_tile_product(g.U, r0, g.n, Ms, acc);
-        if constexpr (MODE == BC_UPDATE) {
-            d4 acc2[4];
-            bc_tile_product(g.U2, r0, g.n, Ms, acc2);
+        bc_tile_product(ca, Ms, acc);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = r0 + rq + 4 * v;
-                if (row >= g.n) continue;
-                const double di = g.dinv[row];
+        for (int v = 0; v < 4; ++v) {
+            const int row = r0 + rq + 4 * v;
+            if (row >= g.n) continue;
+            double di = 0.0;
+            if constexpr (MODE == BC_RUP) di = g.dinv[row];
 #pragma unroll
-                for (int jb = 0; jb < 4; ++jb) {
-                    const size_t o = (size_t)row * kB + 16 * jb + cq;
+            for (int jb = 0; jb < 4; ++jb) {
+                const size_t o = (size_t)row * kB + 16 * jb + cq;
+                if constexpr (MODE == BC_XUP) {
                     g.Y[o] = g.Y[o] + acc[jb][v];
-                    const double r = g.Y2[o] - acc2[jb][v];
-                    g.Y2[o] = r;
-                    ((double*)g.Z)[o] = di * r;
+                } else if constexpr (MODE == BC_RUP) {
+                    const double r = g.Y[o] - acc[jb][v];
+                    g.Y[o] = r;
+                    g.Z[o] = di * r;
                     nrm[jb] += r * r;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = r0 + rq + 4 * v;
-                if (row >= g.n) continue;
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb) {
-                    const size_t o = (size_t)row * kB + 16 * jb + cq;
-                    g.Y[o] = MODE == BC_DIR ? g.Z[o] + acc[jb][v] : acc[jb][v];
+                } else if constexpr (MODE == BC_DIR) {
+                    g.Y[o] = g.Z[o] + acc[jb][v];
+                } else {
+                    g.Y[o] = acc[jb][v];
                 }
             }
         }
     }
-    if constexpr (MODE == BC_UPDATE) {
+    if constexpr (MODE == BC_RUP) {
         // Column 16 jb + cq: lanes cq, cq + 16, cq + 32, cq + 48, then the waves in order.
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) {
@@ -336,10 +376,12 @@ constexpr int kSP = 65;  // LDS pitch
 // columns in order.  mode 0: every column in `use` must have a positive pivot
 // (bad = 1 otherwise); mode 1: a column whose pivot is <= tau is dropped.
 // keep[k] is set for the factored columns; dropped or unused columns of A
-// become zero.
+// become zero.  Thread t: lane j = t % 64 owns column j; wave g updates the
+// rows i = g (mod 4), so every LDS access of a wave is one row (conflict
+// free) or a broadcast.
 __device__ void small_cholesky(double* A, const int* use, int mode, double tau, int* keep, int* bad)
 {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, j = t & 63, g = t >> 6;
     for (int k = 0; k < kB; ++k) {
         __syncthreads();
         const double d = A[k * kSP + k];
@@ -361,14 +403,15 @@ __device__ void small_cholesky(double* A, const int* use, int mode, double tau, 
             continue;
         }
         const double piv = sqrt(d), ip = 1.0 / piv;
-        if (t < kB && t > k) A[t * kSP + k] *= ip;
-        if (t == k) A[k * kSP + k] = piv;
+        if (t < kB) {
+            if (t > k) A[t * kSP + k] *= ip;
+            else if (t == k) A[k * kSP + k] = piv;
+        }
         __syncthreads();
-        // Trailing update of the lower triangle: thread t takes column j = t % 64, rows i = j, j + 4, ...
-        const int j = t & 63;
-        if (j > k) {
-            const double ljk = A[j * kSP + k];
-            for (int i = j + (t >> 6); i < kB; i += 4) A[i * kSP + j] -= A[i * kSP + k] * ljk;
+        const double ljk = j > k ? A[j * kSP + k] : 0.0;
+        for (int i = k + 1 + ((g - (k + 1)) & 3); i < kB; i += 4) {
+            const double lik = A[i * kSP + k];
+            if (j > k && j <= i) A[i * kSP + j] -= lik * ljk;
         }
     }
     __syncthreads();
@@ -376,8 +419,9 @@ __device__ void small_cholesky(double* A, const int* use, int mode, double tau, 
 
 // X = Lk^-1 for the lower-triangular factor restricted to the kept columns
 // (rows and columns not kept are zero in X).  Row by row: X[i][j] =
-// (delta_ij - sum_{m=j}^{i-1} L[i][m] X[m][j]) / L[i][i], the sum split over
-// four thread groups and added in group order.
+// (delta_ij - sum_{m<i} L[i][m] X[m][j]) / L[i][i] (X[m][j] = 0 for m < j);
+// wave g adds the terms m = g (mod 4) for lane j, and the four wave sums are
+// added in wave order.  L[i][m] is a broadcast and X[m][.] one row.
 __device__ void small_tri_inverse(const double* Lm, const int* keep, double* X, double* tmp)
 {
     const int t = threadIdx.x, j = t & 63, g = t >> 6;
@@ -386,8 +430,7 @@ __device__ void small_tri_inverse(const double* Lm, const int* keep, double* X, 
         __syncthreads();
         if (!keep[i]) continue;
         double s = 0.0;
-        if (keep[j] && j < i)
-            for (int m = j + g; m < i; m += 4) s += Lm[i * kSP + m] * X[m * kSP + j];
+        for (int m = g; m < i; m += 4) s += Lm[i * kSP + m] * X[m * kSP + j];
         tmp[g * kB + j] = s;
         __syncthreads();
         if (t < kB && keep[j] && j <= i) {
@@ -484,20 +527,14 @@ __global__ __launch_bounds__(kSmallBS) void k_bc_alpha(BcState* st, int gate)
     if (!finite && threadIdx.x == 0) st->status = BC_BREAKDOWN;
 }
 
-// Reduce the column norms of the updated residual, apply the stopping tests,
-// and if the iteration continues: M = beta = -Li' (Li Q'Z) (G0 = Q'Z).
-__global__ __launch_bounds__(kSmallBS) void k_bc_beta(BcState* st, const double* __restrict__ part, int G, int gate)
+// Apply the stopping tests to the column norms of the updated residual
+// (st->rr) and, if the iteration continues, M = beta = -Li' (Li Q'Z) (G0 = Q'Z).
+__global__ __launch_bounds__(kSmallBS) void k_bc_beta(BcState* st, int gate)
 {
     if (bc_stopped(st, gate)) return;
     __shared__ double A[kB * kSP], X[kB * kSP], T[kB * kSP];
     __shared__ int decide;
     const int t = threadIdx.x;
-    if (t < kB) {
-        double s = 0.0;
-        for (int g = 0; g < G; ++g) s += part[(size_t)g * kB + t];
-        st->rr[t] = s;
-    }
-    __syncthreads();
     if (t == 0) {
         bool pass = true, finite = true;
         for (int j = 0; j < kB; ++j) {
@@ -686,16 +723,24 @@ struct BcOps {
         const int nop = V1 ? 2 : 1;
         void* a[] = {&n, &U, &V0, &V1, &b->part, &b->gram_rpw, &b->gram_G, &b->st, &gate};
         launch(nop == 2 ? (const void*)k_bc_gram<2> : (const void*)k_bc_gram<1>, b->gram_G, kGramBS, st, a);
-        void* r[] = {&b->part, &b->gram_G, (void*)&nop, &b->st, &gate};
-        launch((const void*)k_bc_reduce, nop * kBB / 256, 256, st, r);
+        int count = nop * kBB, which = 0;
+        void* r[] = {&b->part, &b->gram_G, &count, &which, &b->st, &gate};
+        launch((const void*)k_bc_sum<32>, count / 32, 256, st, r);
     }
-    void gemm(int mode, const double* U, const double* U2, double* Y, double* Y2, const double* Z, int gate)
+    void norms(int gate)
     {
-        BcGemmArgs g{c->n, U, U2, Y, Y2, Z, c->dinv, b->part2, b->gemm_G};
+        int count = kB, which = 1;
+        void* r[] = {&b->part2, &b->gemm_G, &count, &which, &b->st, &gate};
+        launch((const void*)k_bc_sum<4>, kB / 4, 256, st, r);
+    }
+    void gemm(int mode, const double* U, double* Y, double* Z, int gate)
+    {
+        BcGemmArgs g{c->n, U, Y, Z, c->dinv, b->part2, b->gemm_G};
         void* a[] = {&g, &b->st, &gate};
-        const void* fn = mode == BC_UPDATE ? (const void*)k_bc_gemm<BC_UPDATE>
-                         : mode == BC_DIR  ? (const void*)k_bc_gemm<BC_DIR>
-                                           : (const void*)k_bc_gemm<BC_APPLY>;
+        const void* fn = mode == BC_XUP   ? (const void*)k_bc_gemm<BC_XUP>
+                         : mode == BC_RUP ? (const void*)k_bc_gemm<BC_RUP>
+                         : mode == BC_DIR ? (const void*)k_bc_gemm<BC_DIR>
+                                          : (const void*)k_bc_gemm<BC_APPLY>;
         launch(fn, b->gemm_G, kGemmBS, st, a);
     }
     void orth_pass(int pass, int gate)
@@ -708,13 +753,13 @@ struct BcOps {
     {
         gram(W0, W0, nullptr, gate);
         orth_pass(0, gate);
-        gemm(BC_APPLY, W0, nullptr, Wa, nullptr, nullptr, gate);
+        gemm(BC_APPLY, W0, Wa, nullptr, gate);
         gram(Wa, Wa, nullptr, gate);
         orth_pass(1, gate);
-        gemm(BC_APPLY, Wa, nullptr, Wb, nullptr, nullptr, gate);
+        gemm(BC_APPLY, Wa, Wb, nullptr, gate);
         gram(Wb, Wb, nullptr, gate);
         orth_pass(2, gate);
-        gemm(BC_APPLY, Wb, nullptr, v.P, nullptr, nullptr, gate);
+        gemm(BC_APPLY, Wb, v.P, nullptr, gate);
     }
     // R = B - A X, Z = M^-1 R (write), partials of r'r, b'b; then the scalars.
     void residual(int write, int mode)
@@ -734,11 +779,13 @@ struct BcOps {
         int gate = 1;
         void* a[] = {&b->st, &gate};
         launch((const void*)k_bc_alpha, 1, kSmallBS, st, a);
-        gemm(BC_UPDATE, v.P, v.Q, v.X, v.R, v.Z, 1);
+        gemm(BC_XUP, v.P, v.X, nullptr, 1);
+        gemm(BC_RUP, v.Q, v.R, v.Z, 1);
+        norms(1);
         gram(v.Q, v.Z, nullptr, 1);
-        void* bta[] = {&b->st, &b->part2, &b->gemm_G, &gate};
+        void* bta[] = {&b->st, &gate};
         launch((const void*)k_bc_beta, 1, kSmallBS, st, bta);
-        gemm(BC_DIR, v.P, nullptr, v.W, nullptr, v.Z, 1);
+        gemm(BC_DIR, v.P, v.W, v.Z, 1);
         // W -> Z -> Q -> P (Z and Q are free until the next iteration's product)
         orth(v.W, v.Z, v.Q, 1);
     }
