@@ -448,6 +448,51 @@ def bench_multi(args, a, b, s):
     return out
 
 
+def bench_q1(args, *_):
+    """The Q1 operator from element coefficients on the device: the matrix-free
+    product against the CSR product of the same operator, and device assembly."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1107_0538_amd import Solver, q1_apply, q1_assemble
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for n in (51, 128):
+        sig = W.element_sigma(n, np.random.default_rng(0))  # the seed-0 problem's coefficients
+        sig_d = torch.as_tensor(sig, device=dev)
+        N, E = n ** 3, (n - 1) ** 3
+        x = torch.as_tensor(np.random.default_rng(1).uniform(-1, 1, N), device=dev)
+        y = torch.empty_like(x)
+        q1_apply(n, sig_d, x, y)
+        t_mf = device_timed(stream, lambda: q1_apply(n, sig_d, x, y), 100)
+        m = q1_assemble(n, sig_d)
+        torch.cuda.synchronize()
+        t_as = device_timed(stream, lambda: q1_assemble(n, sig_d), 5)
+        t0 = time.perf_counter()
+        W.assemble(n, sig)
+        t_host = time.perf_counter() - t0
+        sc = Solver(m)
+        y2 = torch.empty_like(x)
+        sc.spmv(x, y2)
+        t_csr = device_timed(stream, lambda: sc.spmv(x, y2), 100)
+        same = bool(torch.equal(y, y2))
+        mf_bytes = 8 * N + 8 * E + 8 * N
+        csr_bytes = spmv_bytes(N, m.nnz)
+        out[f"{n}^3"] = {
+            "n": N, "nnz": m.nnz, "apply_us": t_mf * 1e6, "apply_bytes": mf_bytes, "apply_gbs": mf_bytes / t_mf / 1e9,
+            "csr_spmv_us": t_csr * 1e6, "csr_bytes": csr_bytes, "bytes_ratio": csr_bytes / mf_bytes,
+            "speedup_vs_csr": t_csr / t_mf, "bitwise_equal_to_csr_product": same,
+            "device_assembly_ms": t_as * 1e3, "host_assembly_ms": t_host * 1e3,
+        }
+        log(f"q1 {n}^3: matrix-free {t_mf * 1e6:.1f} us ({mf_bytes / 1e6:.1f} MB) vs CSR {t_csr * 1e6:.1f} us "
+            f"({csr_bytes / 1e6:.1f} MB); assembly {t_as * 1e3:.2f} ms on the device, {t_host * 1e3:.0f} ms host")
+        del sc, m
+    return out
+
+
 def bench_learned(args, a, b, s):
     """POD + MLP warm start on the 2000-source family: held-out solve time and iterations."""
     import numpy as np
@@ -526,7 +571,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch shape by timing (default: the library's default shape, the one profiled)")
     ap.add_argument("--no-autotune", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--forms", default="mixed,batched,multi,learned",
+    ap.add_argument("--forms", default="mixed,batched,multi,q1,learned",
                     help="comma list of the forms measured against FP64 (empty: none)")
     ap.add_argument("--learned-eval", type=int, default=500, help="held-out right-hand sides evaluated")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -700,7 +745,8 @@ def main():
     if forms:
         out["forms_vs_fp64"] = {}
     for f in forms:
-        fn = {"mixed": bench_mixed, "batched": bench_batched, "multi": bench_multi, "learned": bench_learned}[f]
+        fn = {"mixed": bench_mixed, "batched": bench_batched, "multi": bench_multi, "q1": bench_q1,
+              "learned": bench_learned}[f]
         log(f"form {f}")
         try:
             out["forms_vs_fp64"][f] = fn(args, a, b, s)

@@ -329,6 +329,37 @@ int pod_decode(const double *Phi, int64_t n, int32_t k, int64_t ldphi, const flo
                const double *scale, const double *shift, double *X, void *hip_stream);
 
 /*
+ * The Q1 hexahedral operator of the finite-element case study (Section IV)
+ * on a structured grid, built from the element coefficients on the device:
+ * -div(sigma grad u) + c u discretised with trilinear hexahedra on the unit
+ * cube, n_edge nodes per edge (N = n_edge^3, h = 1 / (n_edge - 1)), one
+ * coefficient per element.  Nodes are numbered x + n y + n^2 z (x fastest),
+ * elements the same with n_edge - 1; every node is kept (no boundary rows
+ * removed), so the 27-point pattern has (3 n_edge - 2)^3 entries.  Between
+ * two nodes that differ in d coordinates an element adds
+ * sigma_e h Khat(d) + c h^3 Mhat(d), Khat = (1/3, 0, -1/12, -1/12),
+ * Mhat(d) = (1/3)^(3-d) (1/6)^d; a_ij sums this over the elements holding
+ * both nodes, in ascending element order.
+ * sigma: device FP64 array of (n_edge - 1)^3 element coefficients; c >= 0;
+ * 2 <= n_edge and (3 n_edge - 2)^3 < 2^31.  Asynchronous on hip_stream.
+ * Returns 0, CG_EINVAL or CG_EHIP.
+ *
+ * q1_apply:    y = A x without forming A (device x, y of N entries, x != y).
+ *              Reads x, sigma and writes y: about 24 N bytes against the
+ *              12 nnz + 4 (N + 1) + 16 N of the CSR product.  Each row adds
+ *              its 27 products in ascending column order, so the result is
+ *              bitwise the sequential product of the matrix q1_assemble
+ *              writes.
+ * q1_assemble: the same A in CSR: rowptr int32[N + 1], col int32[nnz]
+ *              (ascending per row, diagonal included), val FP64[nnz], all
+ *              device memory owned by the caller (nnz = (3 n_edge - 2)^3).
+ *              The arrays can be passed to cg_create with CG_MEM_DEVICE.
+ */
+int q1_apply(int32_t n_edge, double c, const double *sigma, const double *x, double *y, void *hip_stream);
+int q1_assemble(int32_t n_edge, double c, const double *sigma, int32_t *rowptr, int32_t *col, double *val,
+                void *hip_stream);
+
+/*
  * Multilayer perceptron of the learned warm start (maps source parameters to
  * POD coefficients): nlayers affine layers with dims[0..nlayers] widths,
  * SiLU after every hidden layer, linear output, loss = mean squared error

@@ -5,4 +5,4 @@ this package binds its C-ABI (include/jpcg.h) with ctypes and uses torch only
 for device tensors and streams.
 """
 from . import capi  # noqa: F401
-from .solver import Batch, Solver  # noqa: F401
+from .solver import Batch, DeviceCSR, Solver, q1_apply, q1_assemble  # noqa: F401

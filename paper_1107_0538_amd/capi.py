@@ -87,6 +87,8 @@ SIGNATURES = {
                                   ctypes.c_int64, _P]),
     "pod_decode": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_int32, _P, _P,
                                   _P, _P]),
+    "q1_apply": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P]),
+    "q1_assemble": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, _P, _P, _P, _P, _P]),
     "mlp_create": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32, _P, ctypes.POINTER(_P)]),
     "mlp_param_count": (ctypes.c_int64, [_P]),
     "mlp_set_params": (ctypes.c_int, [_P, _P]),

@@ -287,3 +287,54 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# -- structured Q1 operator from element coefficients (no CSR on the host) -----------------
+def _q1_check(n_edge, sigma):
+    torch = _torch()
+    if n_edge < 2:
+        raise ValueError("n_edge must be at least 2")
+    if not isinstance(sigma, torch.Tensor) or not sigma.is_cuda or sigma.dtype != torch.float64 \
+            or sigma.numel() != (n_edge - 1) ** 3 or not sigma.is_contiguous():
+        raise ValueError("sigma must be a contiguous float64 CUDA tensor of (n_edge - 1)^3 element coefficients")
+
+
+def q1_apply(n_edge, sigma, x, y=None, c=1e-3, stream=None):
+    """y = A x for the Q1 operator of the element coefficients sigma, without forming A."""
+    torch = _torch()
+    _q1_check(n_edge, sigma)
+    _as_device_vec(x, n_edge ** 3, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _as_device_vec(y, n_edge ** 3, "y")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    capi.check(capi.load().q1_apply(int(n_edge), float(c), sigma.data_ptr(), x.data_ptr(), y.data_ptr(),
+                                    ctypes.c_void_p(st.cuda_stream)))
+    return y
+
+
+class DeviceCSR:
+    """A CSR matrix in device memory (torch tensors), accepted by Solver."""
+
+    def __init__(self, n, rowptr, col, val):
+        self.n, self.rowptr, self.col, self.val = n, rowptr, col, val
+
+    @property
+    def nnz(self):
+        return int(self.col.numel())
+
+
+def q1_assemble(n_edge, sigma, c=1e-3, stream=None) -> DeviceCSR:
+    """The Q1 operator of the element coefficients sigma, assembled in CSR on the device."""
+    torch = _torch()
+    _q1_check(n_edge, sigma)
+    n = n_edge ** 3
+    nnz = (3 * n_edge - 2) ** 3
+    dev = sigma.device
+    rowptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    capi.check(capi.load().q1_assemble(int(n_edge), float(c), sigma.data_ptr(), rowptr.data_ptr(), col.data_ptr(),
+                                       val.data_ptr(), ctypes.c_void_p(st.cuda_stream)))
+    return DeviceCSR(n, rowptr, col, val)

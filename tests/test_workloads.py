@@ -131,3 +131,51 @@ def test_stored_oracle_values_128():
     st = g["forms"]["standard"]
     assert st["status"] == 0 and st["relres_true"] <= 1e-10 and 0 < st["iters"] <= g["n"]
     assert len(st["x_rows"]) == 1024 and st["x_norm"] > 0
+
+
+def test_elementwise_q1_oracle_matches_the_assembled_matrix():
+    # Two independent builds of the same operator: the generator's entry
+    # tables (assembled CSR, multiplied by the C oracle) and the element-by-
+    # element oracle with element matrices from 1-D Kronecker products.
+    import oracle
+    import oracle.q1 as q1
+
+    for n in (2, 3, 6, 11):
+        rng = np.random.default_rng(n)
+        sig = np.exp(rng.standard_normal((n - 1,) * 3))
+        a = W.assemble(n, sig, 1e-3)
+        x = rng.standard_normal(n ** 3)
+        y = q1.apply(n, sig, 1e-3, x)
+        yo = oracle.spmv(a, x)
+        rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+        absax = np.bincount(rows, weights=np.abs(a.val * x[a.col]), minlength=a.n)
+        assert np.all(np.abs(y - yo) <= 1e-14 * absax)
+        # The element-wise rounding scale bounds the assembled row's sum_j |a_ij x_j|.
+        assert np.all(q1.abs_row_bound(n, sig, 1e-3, x) >= absax * (1 - 1e-12))
+        X = rng.standard_normal((n ** 3, 3))
+        y1 = q1.apply(n, sig, 1e-3, X[:, 1])
+        assert np.allclose(q1.apply(n, sig, 1e-3, X)[:, 1], y1, rtol=0, atol=1e-14 * np.max(np.abs(y1)))
+        d = q1.diagonal(n, sig, 1e-3)
+        dd = a.to_dense().diagonal() if n <= 6 else np.array(
+            [a.val[a.rowptr[i]:a.rowptr[i + 1]][a.col[a.rowptr[i]:a.rowptr[i + 1]] == i][0] for i in range(a.n)])
+        assert np.allclose(d, dd, rtol=1e-14, atol=0)
+
+
+def test_elementwise_q1_oracle_invariants():
+    import oracle.q1 as q1
+
+    n = 7
+    rng = np.random.default_rng(3)
+    sig = np.exp(rng.standard_normal((n - 1,) * 3))
+    # K 1 = 0: the operator maps the constant to c M 1, and 1'A1 = c |Omega|.
+    y = q1.apply(n, sig, 1e-3, np.ones(n ** 3))
+    ym = q1.apply(n, np.zeros_like(sig), 1.0, np.ones(n ** 3))
+    assert np.allclose(y, 1e-3 * ym, rtol=1e-12, atol=1e-18)
+    assert abs(y.sum() - 1e-3) <= 1e-15
+    # Symmetric: x'A y = y'A x.
+    x, z = rng.standard_normal(n ** 3), rng.standard_normal(n ** 3)
+    assert abs(x @ q1.apply(n, sig, 1e-3, z) - z @ q1.apply(n, sig, 1e-3, x)) <= 1e-12 * abs(x @ q1.apply(n, sig, 1e-3, z))
+    # Element matrices: K_e 1 = 0, 1'M_e 1 = h^3, textbook diagonal 8/3 s... in units of h.
+    K, M = q1.element_matrices(0.5)
+    assert np.allclose(K @ np.ones(8), 0.0) and np.isclose(M.sum(), 0.5 ** 3)
+    assert np.allclose(np.diag(K), 0.5 / 3.0) and np.allclose(np.diag(M), 0.5 ** 3 / 27.0)
