@@ -38,6 +38,36 @@ def test_spmm_bitwise(cuda, n, s):
         assert np.array_equal(Y[:, j], oracle.spmv(a, X[:, j])), j
 
 
+@pytest.mark.parametrize("s", [64, 3])
+def test_spmm_bitwise_ragged_and_hub_rows(cuda, s):
+    # Short rows and four hub rows of more than 1024 nonzeros (many gather
+    # batches per row, the tail batch reading into the arrays' zero pad).
+    from test_gpu_pcg import ragged_matrix
+
+    from paper_1107_0538_amd import Solver
+
+    a = ragged_matrix()
+    X = np.random.default_rng(s).uniform(-1, 1, (a.n, s))
+    Y = Solver(a).spmm(_t(X, cuda)).cpu().numpy()
+    for j in range(s):
+        assert np.array_equal(Y[:, j], oracle.spmv(a, X[:, j])), j
+
+
+def test_multi_rhs_solve_on_ragged_rows(cuda):
+    from test_gpu_pcg import ragged_matrix
+
+    from paper_1107_0538_amd import Solver
+
+    a = ragged_matrix(seed=1)
+    B = np.random.default_rng(4).uniform(-1, 1, (a.n, 8))
+    X, infos = Solver(a).solve_multi(_t(B, cuda))
+    X = X.cpu().numpy()
+    for j in range(8):
+        xo, io = oracle.pcg(a, B[:, j])
+        assert infos[j]["status"] == io["status"] and abs(infos[j]["iters"] - io["iters"]) <= 2
+        assert np.linalg.norm(X[:, j] - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
 @pytest.mark.parametrize("s", [64, 5])
 def test_multi_rhs_parity_16(cuda, s):
     from paper_1107_0538_amd import Solver
