@@ -534,12 +534,33 @@ def bench_learned(args, a, b, s):
         y = learned.dense_gram(ws.Phi, Bh[j].reshape(n, 1))
         return learned.dense_gemm(ws.Phi, learned.dense_gemm(Hinv, y)).reshape(-1)
 
+    # The solutions of the held-out right-hand sides (from x0 = 0, to the same
+    # tolerance) give the exact projection start x0 = Phi Phi' x*, the best any
+    # network can do in this basis, and the held-out loss of the network.
+    xstar = torch.empty((n, len(held)), dtype=torch.float64, device=dev)
+    for j in range(len(held)):
+        xj = torch.zeros(n, dtype=torch.float64, device=dev)
+        info = s.cg_solve(Bh[j], xj, tol=tol)
+        assert info["status"] == 0
+        xstar[:, j] = xj
+    c_star = learned.dense_gram(ws.Phi, xstar)  # k x held
+    c_np = c_star.cpu().numpy().T
+    t_held = (c_np - ws.mu) / ws.sigma
+    pred = np.concatenate([ws.predict(theta[held[c:c + 256]]).cpu().numpy() for c in range(0, len(held), 256)])
+    pred = pred.astype(np.float64)
+    held_loss = float(np.mean((pred - t_held) ** 2))
+
+    def x0_proj(j, i):
+        return learned.dense_gemm(ws.Phi, c_star[:, j:j + 1].contiguous()).reshape(-1)
+
     out = {"tol": tol, "family": "8 Gaussian sources, centres U[0,1]^3 (theta = 24 numbers), widths U[.02,.1], "
                      "amplitudes N(0,1) fixed; b = M f", "pod_modes": 64, "snapshots": 500, "train": 1500,
            "held_out": len(held), "network": "24-256-256-64 bf16 (fp32 accumulation, fp32 master weights)",
-           "epochs": args.learned_epochs, "final_train_loss": ws.loss_curve[-1][1], **ws.timings,
+           "epochs": args.learned_epochs, "final_train_loss": ws.loss_curve[-1][1], "held_out_loss": held_loss,
+           **ws.timings,
            "pod_energy_captured": float(ws.energy[:64].sum() / max(ws.energy.sum(), 1e-300))}
-    for name, fx in (("zero", x0_zero), ("mlp", x0_mlp), ("const", x0_const), ("galerkin", x0_galerkin)):
+    for name, fx in (("zero", x0_zero), ("mlp", x0_mlp), ("proj", x0_proj), ("const", x0_const),
+                     ("galerkin", x0_galerkin)):
         ts, its, r0 = [], [], []
         for j, i in enumerate(held):
             torch.cuda.synchronize()
@@ -556,6 +577,8 @@ def bench_learned(args, a, b, s):
                      "mean_iters": statistics.mean(its), "median_iters": statistics.median(its)}
         log(f"learned x0={name}: mean {statistics.mean(ts) * 1e3:.2f} ms, mean iters {statistics.mean(its):.1f}")
     out["mlp_vs_zero_time_ratio"] = out["mlp"]["mean_s"] / out["zero"]["mean_s"]
+    out["starts"] = "zero: x0 = 0; mlp: Phi MLP(theta); proj: Phi Phi' x* (exact projection of the solution, " \
+                    "the best start in the basis); const: constant-mode projection; galerkin: Phi (Phi'A Phi)^-1 Phi'b"
     return out
 
 

@@ -119,6 +119,11 @@ typedef struct {
                                /* separately when opts->autotune is set)           */
     double spmv_us;        /* autotuner's best spmv time, 0 if not tuned          */
     double iter_us;        /* autotuner's best solver time per iteration, or 0    */
+    int32_t spmm_blocks_per_cu; /* workgroups per CU of the multi-column product   */
+                                /* (spmm, cg_solve_multi, cg_solve_block): 0 until  */
+                                /* first used; timed at first use with autotune     */
+    int32_t spmm_pad;
+    double spmm_us;        /* autotuner's best 64-column product time, or 0       */
 } cg_config;
 
 typedef struct cg_ctx cg_ctx;

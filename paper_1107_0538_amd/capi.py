@@ -51,7 +51,8 @@ class cg_config(ctypes.Structure):
                 ("tiles", ctypes.c_int32), ("chunk", ctypes.c_int32), ("form", ctypes.c_int32),
                 ("tune_cached", ctypes.c_int32), ("col_bits", ctypes.c_int32),
                 ("spmv_nnz_per_lane", ctypes.c_int32), ("spmv_block_size", ctypes.c_int32),
-                ("spmv_grid", ctypes.c_int32), ("spmv_us", ctypes.c_double), ("iter_us", ctypes.c_double)]
+                ("spmv_grid", ctypes.c_int32), ("spmv_us", ctypes.c_double), ("iter_us", ctypes.c_double),
+                ("spmm_blocks_per_cu", ctypes.c_int32), ("spmm_pad", ctypes.c_int32), ("spmm_us", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

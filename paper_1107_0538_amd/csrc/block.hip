@@ -800,7 +800,8 @@ static cg_block* make_block(cg_ctx* c)
         b->gram_rpw = (c->n + b->gram_G - 1) / b->gram_G;
         const int tiles = (c->n + 15) / 16;
         b->gemm_G = std::max(8, std::min(c->cus * 2, (tiles + 3) / 4) / 8 * 8);
-        b->spmm_G = std::max(8, std::min(c->cus * 4, (c->n + 15) / 16) / 8 * 8);
+        const int wpc = c->opts.autotune ? spmm_blocks_per_cu(c) : 4;
+        b->spmm_G = std::max(8, std::min(c->cus * wpc, (c->n + 15) / 16) / 8 * 8);
         b->spmm_rpb = (c->n + b->spmm_G - 1) / b->spmm_G;
         b->res_G = std::min(1024, (c->n + 3) / 4);
         JPCG_HIP(hipMalloc(&b->work, sizeof(double) * nb * 7));

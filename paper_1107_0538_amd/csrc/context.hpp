@@ -63,6 +63,8 @@ struct cg_ctx {
     int bs = 512;
     int grid = 0;
     int chunk = 16;
+    int spmm_wpc = 0;            // workgroups per CU of the multi-column product (0: not chosen yet)
+    double tuned_spmm_us = 0.0;
     double tuned_spmv_us = 0.0;
     double tuned_iter_us = 0.0;
     bool tune_cached = false;  // the tuned shape came from an earlier context
@@ -79,6 +81,10 @@ int set_error(cg_ctx* c, int code, const std::string& msg);
 
 // Free the multi-RHS solver state of a context (multi.hip).
 void free_multi(cg_ctx* c);
+
+// Workgroups per CU of the multi-column row products, chosen at first use
+// (timed when the context was created with autotune) (multi.hip).
+int spmm_blocks_per_cu(cg_ctx* c);
 
 // Free the block solver state of a context (block.hip).
 void free_block(cg_ctx* c);

@@ -484,15 +484,73 @@ MrArgs<double>& margs<double>(cg_multi* m) { return m->args; }
 template <>
 MrArgs<float>& margs<float>(cg_multi* m) { return m->args32; }
 
+// The multi-column product's grid: workgroups per CU.  Without autotune the
+// default (2); with it, the first use times the 64-column product at 1, 2, 3,
+// 4, 6 and 8 workgroups per CU (rows split evenly, XCD-aware order) and keeps
+// the fastest.
+constexpr int kSpmmDefaultWpc = 2;
+
+int spmm_blocks_per_cu(cg_ctx* c)
+{
+    if (c->spmm_wpc > 0) return c->spmm_wpc;
+    if (!c->opts.autotune) return c->spmm_wpc = kSpmmDefaultWpc;
+    const int s = kCols;
+    const size_t nb = sizeof(double) * (size_t)c->n * s;
+    double *X = nullptr, *Y = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best_w = kSpmmDefaultWpc;
+    float best = 1e30f;
+    try {
+        JPCG_HIP(hipMalloc(&X, nb));
+        JPCG_HIP(hipMalloc(&Y, nb));
+        JPCG_HIP(hipMemsetAsync(X, 0, nb, c->stream));
+        JPCG_HIP(hipEventCreate(&e0));
+        JPCG_HIP(hipEventCreate(&e1));
+        int n = c->n;
+        for (int w : {1, 2, 3, 4, 6, 8}) {
+            int G = std::max(8, std::min(c->cus * w, (c->n + 15) / 16) / 8 * 8);
+            int rpb = (c->n + G - 1) / G;
+            void* args[] = {&n, (void*)&s, &c->rowptr, &c->col, &c->val, &X, &Y, &rpb, &G};
+            JPCG_HIP(hipLaunchKernel((const void*)k_spmm<512, double>, dim3(G), dim3(512), args, 0, c->stream));
+            JPCG_HIP(hipEventRecord(e0, c->stream));
+            constexpr int kReps = 8;
+            for (int r = 0; r < kReps; ++r)
+                JPCG_HIP(hipLaunchKernel((const void*)k_spmm<512, double>, dim3(G), dim3(512), args, 0, c->stream));
+            JPCG_HIP(hipEventRecord(e1, c->stream));
+            JPCG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            JPCG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            ms /= kReps;
+            if (ms < best) {
+                best = ms;
+                best_w = w;
+            }
+        }
+    } catch (...) {
+        if (X) (void)hipFree(X);
+        if (Y) (void)hipFree(Y);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipFree(X);
+    (void)hipFree(Y);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->tuned_spmm_us = best * 1e3;
+    return c->spmm_wpc = best_w;
+}
+
 template <typename T>
 static cg_multi* make_multi(cg_ctx* c, int s)
 {
+    const int wpc = spmm_blocks_per_cu(c);
     cg_multi* m = new cg_multi();
     try {
         m->s = s;
         m->fp32 = sizeof(T) == 4;
         m->chunk = 8;
-        m->G = std::max(8, std::min(c->cus * 2, (c->n + 63) / 64) / 8 * 8);
+        m->G = std::max(8, std::min(c->cus * wpc, (c->n + 63) / 64) / 8 * 8);
         const size_t ns = (size_t)c->n * s;
         JPCG_HIP(hipMalloc(&m->work, sizeof(T) * ns * 7));
         JPCG_HIP(hipMalloc(&m->part, sizeof(double) * (size_t)m->G * 3 * kWave));
@@ -681,7 +739,8 @@ int spmm(cg_ctx* c, const double* X, double* Y, int32_t s)
     if (!c) return CG_EINVAL;
     if (!X || !Y || X == Y || s < 1 || s > kCols) return set_error(c, CG_EINVAL, "spmm: bad arguments");
     try {
-        const int G = std::max(8, std::min(c->cus * 4, (c->n + 15) / 16) / 8 * 8);
+        const int wpc = c->opts.autotune ? spmm_blocks_per_cu(c) : 4;
+        const int G = std::max(8, std::min(c->cus * wpc, (c->n + 15) / 16) / 8 * 8);
         const int rpb = (c->n + G - 1) / G;
         int n = c->n;
         void* args[] = {&n, &s, &c->rowptr, &c->col, &c->val, &X, &Y, (void*)&rpb, (void*)&G};

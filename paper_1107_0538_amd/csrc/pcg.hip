@@ -1152,6 +1152,9 @@ int cg_get_config(cg_ctx* c, cg_config* cfg)
     cfg->spmv_grid = c->spmv ? c->spmv->G : 0;
     cfg->spmv_us = c->tuned_spmv_us;
     cfg->iter_us = c->tuned_iter_us;
+    cfg->spmm_blocks_per_cu = c->spmm_wpc;
+    cfg->spmm_pad = 0;
+    cfg->spmm_us = c->tuned_spmm_us;
     return 0;
 }
 

@@ -5,9 +5,9 @@ Python binds the HIP calls (dense_gram, dense_gemm, pod_decode, mlp_*); the
 dense products, the network's forward/backward/Adam and every CG solve run in
 the library.  The host does the small set-up arithmetic only: the eigen-
 decomposition of the m x m snapshot Gram matrix (m = 500), the per-mode
-standardisation statistics of 2000 x 64 coefficients, and folding the input
-scaling into the first layer's weights (the output de-standardisation is
-applied in FP64 by the decode kernel).
+standardisation statistics of 2000 x 64 coefficients, and the input map
+theta -> 2 theta - 1 of the network's 24 inputs per sample (the output
+de-standardisation is applied in FP64 by the decode kernel).
 """
 from __future__ import annotations
 
@@ -278,7 +278,7 @@ class LearnedWarmStart:
         self.mu = C.mean(0)
         self.sigma = C.std(0) + 1e-300
         T = ((C - self.mu) / self.sigma).astype(np.float32)
-        Xin = (2.0 * self.theta[:self.n_train] - 1.0).astype(np.float32)
+        Xin = self.inputs(self.theta[:self.n_train])
         dims = [Xin.shape[1], *self.hidden, self.k]
         self.net = MLP(dims, self.precision, max_batch=max(batch, 1))
         self.net.set_params(he_uniform(dims, self.seed))
@@ -300,28 +300,27 @@ class LearnedWarmStart:
                         log(f"epoch {ep}: loss {loss:.3e}")
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        self._fold(dims)
+        self._finish()
         self.timings = {"snapshots_s": t1 - t0, "pod_s": t2 - t1, "train_s": t3 - t2,
                         "snapshot_iters_mean": float(np.mean([i["iters"] for i in infos]))}
         return self
 
-    def _fold(self, dims):
-        """Fold the input map theta -> 2 theta - 1 into the first layer (doubling a weight is exact in
-        BF16), so that the network takes raw theta; the output de-standardisation is applied in FP64 by
-        the decode."""
+    def _finish(self):
+        """The output de-standardisation is applied in FP64 by the decode."""
         torch = _torch()
-        p = self.net.get_params().astype(np.float64)
-        W0, b0 = layer_views(p, dims)[0]
-        b0 += -W0.sum(1)
-        W0 *= 2.0
-        self.net.set_params(p.astype(np.float32))
         self.scale = torch.as_tensor(self.sigma, dtype=torch.float64, device=self.Phi.device)
         self.shift = torch.as_tensor(self.mu, dtype=torch.float64, device=self.Phi.device)
+
+    @staticmethod
+    def inputs(theta_rows):
+        """Network inputs: theta -> 2 theta - 1 in FP32, exactly as in training (in BF16 mode the
+        forward pass rounds these to BF16, as the training steps did)."""
+        return (2.0 * np.asarray(theta_rows, dtype=np.float64) - 1.0).astype(np.float32)
 
     def predict(self, theta_rows):
         """Standardised FP32 coefficients (len x k) on the device for host theta rows."""
         torch = _torch()
-        X = torch.as_tensor(np.ascontiguousarray(theta_rows, dtype=np.float32), device=self.Phi.device)
+        X = torch.as_tensor(np.ascontiguousarray(self.inputs(theta_rows)), device=self.Phi.device)
         return self.net.forward(X)
 
     def x0(self, theta_rows, out=None):

@@ -185,28 +185,60 @@ def test_mlp_rejects_bad_input(cuda):
 def test_learned_warm_start_gain(cuda):
     # On a family whose solutions lie in a 4-dimensional space the learned
     # start vector must cut CG iterations against x0 = 0 on held-out samples.
+    # Bar: the paired saving (iterations from x0 = 0 minus from the learned
+    # start, per held-out right-hand side) has a mean larger than three of its
+    # standard errors, i.e. the gain is real, not noise of the sample.  The
+    # test also measures what the start is worth: the iterations CG from
+    # x0 = 0 needs to reach the start's residual (its residual history); CG
+    # restarted from the start keeps only part of that, because it rebuilds
+    # the Krylov space (about 19 of 92 iterations here).
     import torch
     from paper_1107_0538_amd import Solver, learned
 
     n = 16
     a, _ = W.problem(n, 0)
     fam = W.amplitude_family(n=n, count=400, k=4, seed=11)
-    s = Solver(a)
+    s = Solver(a, history=True)
     ws = learned.LearnedWarmStart(s, fam, n_pod=100, n_train=300, modes=4, hidden=(64, 64), precision="fp32",
                                   seed=0).fit(epochs=1500, batch=100)
     assert ws.loss_curve[-1][1] < 1e-2
     B = fam.rhs(np.arange(300, 400))
-    its0, its1 = [], []
+    its0, its1, worth = [], [], []
     for j, i in enumerate(range(300, 400)):
         b = _t(B[j], cuda)
         x0 = ws.x0(fam.theta()[i:i + 1]).reshape(-1)
+        r_start = oracle.relres(a, B[j], x0.cpu().numpy())
         x, info = s.solve(b, x0=x0.clone())
         assert info["status"] == 0 and oracle.relres(a, B[j], x.cpu().numpy()) <= tol_recomputed(a.n)
         _, info0 = s.solve(b)
+        hist = s.history()
+        reach = np.flatnonzero(hist <= r_start)
+        worth.append(int(reach[0]) if reach.size else len(hist) - 1)
         its0.append(info0["iters"])
         its1.append(info["iters"])
-    assert np.mean(its1) < 0.9 * np.mean(its0), (np.mean(its0), np.mean(its1))
+    d = np.asarray(its0, float) - np.asarray(its1, float)
+    stderr = d.std(ddof=1) / np.sqrt(d.size)
+    assert d.mean() > 3.0 * stderr, (np.mean(its0), np.mean(its1), np.mean(worth), stderr)
+    assert 0 < d.mean() <= np.mean(worth)
+    print(f"learned start: {np.mean(its0):.1f} -> {np.mean(its1):.1f} iterations; worth {np.mean(worth):.1f}")
     torch.cuda.synchronize()
+
+
+def test_network_inputs_are_the_training_inputs(cuda):
+    # Inference feeds the network exactly the inputs training used (2 theta - 1
+    # in FP32, rounded to BF16 inside the forward pass), so a BF16 network's
+    # prediction equals its forward pass on the training inputs bit for bit.
+    import torch
+    from paper_1107_0538_amd import Solver, learned
+
+    n = 8
+    a, _ = W.problem(n, 0)
+    fam = W.source_family(n=n, count=64, k=8, seed=3)
+    ws = learned.LearnedWarmStart(Solver(a), fam, n_pod=16, n_train=48, modes=8, hidden=(32, 32),
+                                  precision="bf16").fit(epochs=3, batch=16)
+    th = fam.theta()[48:64]
+    X = torch.as_tensor((2.0 * th - 1.0).astype(np.float32), device=cuda)
+    assert torch.equal(ws.predict(th), ws.net.forward(X))
 
 
 def test_learned_pipeline_source_family(cuda):

@@ -230,3 +230,29 @@ def test_multi_rhs_mixed_columns_and_limits(cuda):
     assert all(i["status"] == 1 and i["outer"] == 1 for i in infos)
     with pytest.raises(ValueError):
         Solver(a).solve_multi_mixed(_t(Bg, cuda))
+
+
+def test_autotuned_multi_column_product(cuda):
+    # With autotune the first multi-column use times the product's grid; the
+    # products and solves are unchanged bitwise / within the solver's bar.
+    from paper_1107_0538_amd import Solver
+
+    a = mat(16)
+    s = Solver(a, autotune=True)
+    X = np.random.default_rng(3).uniform(-1, 1, (a.n, 64))
+    Y = s.spmm(_t(X, cuda)).cpu().numpy()
+    for j in (0, 17, 63):
+        assert np.array_equal(Y[:, j], oracle.spmv(a, X[:, j]))
+    cfg = s.config()
+    assert cfg["spmm_blocks_per_cu"] in (1, 2, 3, 4, 6, 8) and cfg["spmm_us"] > 0
+    B = W.multi_rhs(a.n, 8)
+    Xm, infos = s.solve_multi(_t(B, cuda))
+    Xm = Xm.cpu().numpy()
+    for j in range(8):
+        xo, io = oracle.pcg(a, B[:, j])
+        assert abs(infos[j]["iters"] - io["iters"]) <= 2
+        assert np.linalg.norm(Xm[:, j] - xo) <= 1e-8 * np.linalg.norm(xo)
+    Xb, binfo = s.solve_block(_t(B, cuda))
+    assert binfo[0]["status"] == 0
+    for j in range(8):
+        assert oracle.relres(a, B[:, j], Xb.cpu().numpy()[:, j]) <= tol_recomputed(a.n)
