@@ -288,16 +288,35 @@ def bench_mixed(args, a51, b51, s51):
             xmx.zero_()
             return smx.cg_solve_mixed(bt, xmx)
 
+        xmm = torch.zeros_like(bt)
+
+        def fmm():
+            xmm.zero_()
+            return smx.cg_solve_mixed_matrix(bt, xmm)
+
         reps = max(3, min(args.steps, 10))
-        f64(), fmx()
+        f64(), fmx(), fmm()
         t64, _, i64 = _timed(f64, reps)
         tmx, _, imx = _timed(fmx, reps)
+        tmm, _, imm = _timed(fmm, reps)
+        x64h = x64.cpu().numpy()
+        dmm = x64h - x64h.mean()
+        xmmh = xmm.cpu().numpy()
+        mm = {"s": tmm, "speedup": t64 / tmm, "iters": imm["iters"], "replacements": imm["replacements"],
+              "relres_true": imm["relres_true"], "status": imm["status"],
+              "vs_fp64_solution_relerr": float(np.linalg.norm(xmmh - x64h) / np.linalg.norm(x64h)),
+              "vs_fp64_solution_relerr_mean_removed": float(np.linalg.norm((xmmh - xmmh.mean()) - dmm) /
+                                                            np.linalg.norm(dmm)),
+              "us_per_iter": imm["seconds"] / max(imm["iters"], 1) * 1e6}
+        log(f"fp32-matrix {n}^3: {tmm * 1e3:.2f} ms, {imm['iters']} iterations, {imm['replacements']} replacements "
+            f"({t64 / tmm:.2f}x FP64)")
         err = float(torch.linalg.vector_norm(xmx - x64) / torch.linalg.vector_norm(x64))
         out[f"{n}^3"] = {
             "n": a.n, "nnz": a.nnz, "fp64_s": t64, "mixed_s": tmx, "speedup": t64 / tmx,
             "fp64_iters": i64["iters"], "mixed_inner_iters": imx["iters"], "mixed_outer": imx["outer"],
             "mixed_relres_true": imx["relres_true"], "fp64_relres_true": i64["relres_true"],
             "mixed_vs_fp64_solution_relerr": err, "status": [i64["status"], imx["status"]],
+            "fp32_matrix": mm,
         }
         log(f"mixed {n}^3: fp64 {t64 * 1e3:.2f} ms, mixed {tmx * 1e3:.2f} ms ({imx['outer']} outer, "
             f"{imx['iters']} inner), err vs fp64 {err:.1e}")

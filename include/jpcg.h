@@ -177,6 +177,25 @@ int cg_solve(cg_ctx *ctx, const double *b, double *x, double tol, int32_t maxit,
 int cg_solve_mixed(cg_ctx *ctx, const double *b, double *x, double tol, int32_t maxit_outer,
                    double tol_inner, int32_t maxit_inner, cg_info *info);
 
+/*
+ * Mixed precision that keeps the FP64 iteration: the iteration's sparse
+ * products stream the FP32 copy of the values (4 instead of 8 bytes per
+ * nonzero) in the row-sum-preserving evaluation
+ *     (A p)_i ~ sum_j fl32(a_ij) (p_j - p_i) + s_i p_i,   s_i = sum_j a_ij in FP64,
+ * while every vector, dot product and scalar stays FP64 (cg_solve's standard
+ * form).  The perturbation fl32(a_ij) - a_ij leaves A 1 exact, so the near-
+ * constant modes of these systems are not disturbed; the drift of the
+ * recurrence residual from b - A x that the rest of it causes is removed by
+ * reliable updates (Sleijpen and van der Vorst): whenever the recurrence
+ * residual has fallen by the factor drop since the last replacement (0 =
+ * 1e-2; 0 < drop < 1), and at the continue-condition, the FP64 true residual
+ * either confirms convergence or replaces r, and the iteration continues.
+ * Requires fp32_copy.  Same arguments, statuses and info as cg_solve
+ * (replacements counts every replaced residual).
+ */
+int cg_solve_mixed_matrix(cg_ctx *ctx, const double *b, double *x, double tol, int32_t maxit, double drop,
+                          cg_info *info);
+
 /* y = A x (the paper's "DGEMV(sparse)").  Device pointers to float64[n], x != y.
  * Rows are summed in stored order (bitwise the sequential CSR product), with
  * the product's own tiling and grid (cg_config.spmv_*).  Asynchronous on the

@@ -5,7 +5,7 @@ paper and from textbook definitions.  Only the tests, the smoke check and the
 benchmark's CPU-baseline leg may import this package; the GPU library and its
 Python binding never do, and this package never imports them.
 
-- `pcg`, `spmv`, `residual`, `dot`: FP64 C code in pcg_oracle.c, loaded
+- `pcg`, `pcg_mixed_matrix`, `spmv`, `residual`, `dot`: FP64 C code in pcg_oracle.c, loaded
   through ctypes (built with gcc, -O2 -ffp-contract=off).  A second build of
   the same source with -fopenmp (`pcg(..., parallel=True)`) exists only to
   time the oracle on all host cores; its dot products sum in another order.
@@ -82,6 +82,9 @@ def _bind(L):
     L.oracle_pcg.restype = ctypes.c_int
     L.oracle_pcg_sr.argtypes = L.oracle_pcg.argtypes
     L.oracle_pcg_sr.restype = ctypes.c_int
+    L.oracle_pcg_m32.argtypes = [ctypes.c_int, P, P, P, P, P, ctypes.c_double, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_double, ctypes.POINTER(OracleInfo)]
+    L.oracle_pcg_m32.restype = ctypes.c_int
     L.oracle_threads.argtypes = []
     L.oracle_threads.restype = ctypes.c_int
     return L
@@ -182,3 +185,18 @@ def pcg(a, b, x0=None, tol: float = 1e-10, maxit: int = 0, precond: str = "jacob
     if trace:
         out.append(tr[: d["iters"] + 1])
     return tuple(out)
+
+
+def pcg_mixed_matrix(a, b, x0=None, tol: float = 1e-10, maxit: int = 0, precond: str = "jacobi",
+                     drop: float = 1e-2, parallel: bool = False):
+    """The FP64 solve whose loop products use the FP32-rounded values in the
+    row-sum-preserving evaluation, confirming on the FP64 true residual each
+    time the residual has fallen by `drop` since the last replacement
+    (oracle_pcg_m32).  Returns (x, info dict)."""
+    rowptr, col, val = _csr_arrays(a)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(a.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    info = OracleInfo()
+    lib(parallel).oracle_pcg_m32(a.n, _p(rowptr), _p(col), _p(val), _p(b), _p(x), tol, a.n if maxit <= 0 else maxit,
+                                 {"none": 0, "jacobi": 1}[precond], float(drop), ctypes.byref(info))
+    return x, info.as_dict()

@@ -405,3 +405,120 @@ out:
     free(diag); free(r); free(u); free(w); free(p); free(sv); free(t);
     return status;
 }
+
+/*
+ * The same Jacobi-PCG solve with the FP32 matrix stream: the products inside
+ * the loop use the values rounded to single precision, in the row-sum-
+ * preserving evaluation
+ *     y_i = sum_k fl32(a_ik) (x[col_k] - x_i) + s_i x_i,   s_i = sum_k a_ik,
+ * (s_i summed in double, in stored order; the terms added in stored order),
+ * with every vector, dot product and scalar in double.  Reliable updates
+ * (Sleijpen and van der Vorst): besides the ordinary continue-condition, the
+ * true residual b - A x with the double values is formed whenever ||r|| has
+ * fallen to `drop` times its value after the last replacement (drop > 0), and
+ * either confirms convergence or replaces r.  Statuses and info as
+ * oracle_pcg; replacements counts every replaced residual.
+ */
+static void spmv_f32_rowsum(int n, const int *rowptr, const int *col, const double *v32, const double *s64,
+                            const double *x, double *y)
+{
+    ORC_PAR
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) s += v32[k] * (x[col[k]] - x[i]);
+        y[i] = s + s64[i] * x[i];
+    }
+}
+
+int oracle_pcg_m32(int n, const int *rowptr, const int *col, const double *val,
+                   const double *b, double *x, double tol, int maxit, int precond,
+                   double drop, oracle_info *info)
+{
+    if (n <= 0 || !rowptr || !col || !val || !b || !x || !info || !(tol >= 0.0) || !(drop >= 0.0))
+        return ORC_EINVAL;
+    if (maxit <= 0) maxit = n;
+    memset(info, 0, sizeof(*info));
+    const int nnz = rowptr[n];
+    double *diag = malloc(sizeof(double) * (size_t)n);
+    double *r = malloc(sizeof(double) * (size_t)n);
+    double *z = malloc(sizeof(double) * (size_t)n);
+    double *p = malloc(sizeof(double) * (size_t)n);
+    double *q = malloc(sizeof(double) * (size_t)n);
+    double *s64 = malloc(sizeof(double) * (size_t)n);
+    double *v32 = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!diag || !r || !z || !p || !q || !s64 || !v32) {
+        free(diag); free(r); free(z); free(p); free(q); free(s64); free(v32);
+        return ORC_ENOMEM;
+    }
+    int status = ORC_MAXIT;
+    for (int k = 0; k < nnz; ++k) v32[k] = (double)(float)val[k];
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) s += val[k];
+        s64[i] = s;
+        diag[i] = 1.0;
+        if (precond == 1) {
+            double d = 0.0;
+            int found = 0;
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+                if (col[k] == i) { d += val[k]; found = 1; }
+            if (!found || !(d > 0.0)) { status = ORC_EDIAG; goto out; }
+            diag[i] = d;
+        }
+    }
+    double nb = sqrt(oracle_dot(n, b, b, 0));
+    if (nb == 0.0) {
+        for (int i = 0; i < n; ++i) x[i] = 0.0;
+        status = ORC_CONVERGED;
+        goto out;
+    }
+    double thr = tol * nb;
+    oracle_spmv(n, rowptr, col, val, x, r);                 /* r0 = b - A x0 with the double values */
+    for (int i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    double rn = sqrt(oracle_dot(n, r, r, 0));
+    info->relres_recur = rn / nb;
+    if (rn <= thr) {
+        info->relres_true = rn / nb;
+        status = ORC_CONVERGED;
+        goto out;
+    }
+    for (int i = 0; i < n; ++i) z[i] = r[i] / diag[i];
+    memcpy(p, z, sizeof(double) * (size_t)n);
+    double rho = oracle_dot(n, r, z, 0);
+    double rref = rn;                                         /* ||r|| after the last replacement */
+    int k = 0;
+    while (k < maxit) {
+        spmv_f32_rowsum(n, rowptr, col, v32, s64, p, q);   /* q = A~ p */
+        double sigma = oracle_dot(n, p, q, 0);
+        if (!(sigma > 0.0) || !isfinite(sigma)) { status = ORC_BREAKDOWN; break; }
+        double alpha = rho / sigma;
+        for (int i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+        for (int i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+        ++k;
+        rn = sqrt(oracle_dot(n, r, r, 0));
+        info->relres_recur = rn / nb;
+        if (rn <= thr || rn <= drop * rref) {
+            oracle_spmv(n, rowptr, col, val, x, q);        /* true residual, double values */
+            for (int i = 0; i < n; ++i) q[i] = b[i] - q[i];
+            double tn = sqrt(oracle_dot(n, q, q, 0));
+            if (tn <= thr) { status = ORC_CONVERGED; break; }
+            memcpy(r, q, sizeof(double) * (size_t)n);       /* residual replacement */
+            info->replacements += 1;
+            rref = tn;
+        }
+        for (int i = 0; i < n; ++i) z[i] = r[i] / diag[i];
+        double rho_new = oracle_dot(n, r, z, 0);
+        if (!(rho_new > 0.0) || !isfinite(rho_new)) { status = ORC_BREAKDOWN; break; }
+        double beta = rho_new / rho;
+        rho = rho_new;
+        for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+    }
+    info->iters = k;
+    oracle_spmv(n, rowptr, col, val, x, q);
+    for (int i = 0; i < n; ++i) q[i] = b[i] - q[i];
+    info->relres_true = sqrt(oracle_dot(n, q, q, 0)) / nb;
+out:
+    info->status = status;
+    free(diag); free(r); free(z); free(p); free(q); free(s64); free(v32);
+    return status;
+}

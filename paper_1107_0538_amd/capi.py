@@ -65,6 +65,8 @@ SIGNATURES = {
     "cg_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(cg_info)]),
     "cg_solve_mixed": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                       ctypes.c_int32, ctypes.POINTER(cg_info)]),
+    "cg_solve_mixed_matrix": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.POINTER(cg_info)]),
     "spmv": (ctypes.c_int, [_P, _P, _P]),
     "jpcg_stream_triad": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, _P]),
     "spmm": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),

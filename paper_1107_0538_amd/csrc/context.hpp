@@ -28,6 +28,7 @@ struct cg_ctx {
     float* val32 = nullptr;   // fp32_copy
     float* dinv32 = nullptr;  // fp32_copy
     float* rowsum32 = nullptr;  // fp32_copy: row sums of A (FP64 sums, FP32 storage)
+    double* rowsum64 = nullptr; // fp32_copy: the same row sums in FP64 (FP32-matrix form)
     std::vector<int> h_rowptr;
 
     // Work vectors for single-RHS solves (one allocation, each vector at a
@@ -43,6 +44,7 @@ struct cg_ctx {
     struct cg_graphs* graphs = nullptr;      // the context's form, FP64
     struct cg_graphs* graphs_std = nullptr;  // standard form FP64 (mixed-form outer residual)
     struct cg_graphs* graphs32 = nullptr;    // standard form FP32 (mixed-form inner solve)
+    struct cg_graphs* graphs_m32 = nullptr;  // standard form FP64 with the FP32 matrix stream
     void* mixed_dev = nullptr;
     void* mixed_host = nullptr;
     struct cg_spmv_plan* spmv = nullptr;     // the standalone product's tiling and grid

@@ -69,13 +69,14 @@ __global__ void jacobi_kernel(int n, const int* __restrict__ rowptr, const int* 
 
 // s_i = sum_j a_ij in FP64, stored in FP32, for the row-sum-preserving FP32 product.
 __global__ void rowsum_kernel(int n, const int* __restrict__ rowptr, const double* __restrict__ val,
-                              float* __restrict__ rs)
+                              float* __restrict__ rs, double* __restrict__ rs64)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double s = 0.0;
     for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) s += val[k];
     rs[i] = (float)s;
+    rs64[i] = s;
 }
 
 __global__ void cast_f32_kernel(int64_t n, const double* __restrict__ in, float* __restrict__ out)
@@ -142,14 +143,16 @@ struct CgKernels {
     const void* sr_restart;
 };
 
-template <int NPL, int BS, typename T>
+// M32: the FP32-matrix form's products (FP32 values, FP64 vectors, row-sum-
+// preserving) for the iteration; set-up, checks and reports keep FP64 values.
+template <int NPL, int BS, typename T, bool M32 = false>
 static CgKernels kernels_for()
 {
     CgKernels k{};
     k.spmv = (const void*)k_spmv<NPL, BS, T>;
     k.setup = (const void*)k_setup<NPL, BS, T>;
-    k.first = (const void*)k_first<NPL, BS, T>;
-    k.direction = (const void*)k_direction<NPL, BS, T>;
+    k.first = (const void*)k_first<NPL, BS, T, M32>;
+    k.direction = (const void*)k_direction<NPL, BS, T, M32>;
     k.update = (const void*)k_update<BS, T>;
     k.check = (const void*)k_check<NPL, BS, T>;
     k.check_decide = (const void*)k_check_decide<BS, T>;
@@ -168,17 +171,17 @@ static CgKernels kernels_for()
 
 // Tile shapes: NPL nonzeros per lane, BS threads; LDS for products is
 // BS * NPL * sizeof(T) bytes.
-template <typename T>
+template <typename T, bool M32 = false>
 static bool kernels_t(int npl, int bs, CgKernels& k)
 {
-    if (npl == 4 && bs == 256) { k = kernels_for<4, 256, T>(); return true; }
-    if (npl == 8 && bs == 256) { k = kernels_for<8, 256, T>(); return true; }
-    if (npl == 16 && bs == 256) { k = kernels_for<16, 256, T>(); return true; }
-    if (npl == 4 && bs == 512) { k = kernels_for<4, 512, T>(); return true; }
-    if (npl == 8 && bs == 512) { k = kernels_for<8, 512, T>(); return true; }
-    if (npl == 16 && bs == 512) { k = kernels_for<16, 512, T>(); return true; }
-    if (npl == 4 && bs == 1024) { k = kernels_for<4, 1024, T>(); return true; }
-    if (npl == 8 && bs == 1024) { k = kernels_for<8, 1024, T>(); return true; }
+    if (npl == 4 && bs == 256) { k = kernels_for<4, 256, T, M32>(); return true; }
+    if (npl == 8 && bs == 256) { k = kernels_for<8, 256, T, M32>(); return true; }
+    if (npl == 16 && bs == 256) { k = kernels_for<16, 256, T, M32>(); return true; }
+    if (npl == 4 && bs == 512) { k = kernels_for<4, 512, T, M32>(); return true; }
+    if (npl == 8 && bs == 512) { k = kernels_for<8, 512, T, M32>(); return true; }
+    if (npl == 16 && bs == 512) { k = kernels_for<16, 512, T, M32>(); return true; }
+    if (npl == 4 && bs == 1024) { k = kernels_for<4, 1024, T, M32>(); return true; }
+    if (npl == 8 && bs == 1024) { k = kernels_for<8, 1024, T, M32>(); return true; }
     return false;
 }
 
@@ -282,16 +285,25 @@ static void fill_args(CgArgsT<T>& a, const SysView<T>& s, const TileMap& tm, int
     a.part_rep = part + 8 * (size_t)G;
     a.st = (CgState*)st;
     a.hist = nullptr;
+    a.rowsum = nullptr;
+    a.val32 = nullptr;
+    a.drop2 = 0.0;
 }
 
 // Build the kernels' arguments and capture the two chunk graphs (first
 // iteration of parity 0 or 1) for one form, precision and launch shape.
-static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, int G, int chunk)
+// mat32: the FP32-matrix form (FP64 standard form whose iteration products
+// stream the FP32 values), confirming on the FP64 true residual each time the
+// recurrence residual has fallen by `drop` since the last replacement.
+static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, int G, int chunk, bool mat32 = false,
+                              double drop = 0.0)
 {
     cg_graphs* g = new cg_graphs();
     try {
-        const bool ok = fp32 ? kernels_t<float>(npl, bs, g->kern) : kernels_t<double>(npl, bs, g->kern);
-        if (!ok || (fp32 && form != CG_FORM_STANDARD)) throw HipError{hipErrorInvalidValue, "launch shape"};
+        const bool ok = fp32 ? kernels_t<float>(npl, bs, g->kern)
+                        : mat32 ? kernels_t<double, true>(npl, bs, g->kern)
+                                : kernels_t<double>(npl, bs, g->kern);
+        if (!ok || ((fp32 || mat32) && form != CG_FORM_STANDARD)) throw HipError{hipErrorInvalidValue, "launch shape"};
         g->form = form;
         g->fp32 = fp32;
         g->npl = npl;
@@ -332,7 +344,11 @@ static cg_graphs* make_graphs(cg_ctx* c, int form, bool fp32, int npl, int bs, i
                                       {(ZPair<double>*)w[1], (ZPair<double>*)w[3]},  // spanning w[1..2], w[3..4]
                                       w[5]},
                       tm, c->n, G, g->part, g->st);
-            g->args.rowsum = nullptr;
+            if (mat32) {
+                g->args.rowsum = c->rowsum64;
+                g->args.val32 = c->val32;
+                g->args.drop2 = drop * drop;
+            }
             SrArgs& sa = g->sargs;
             sa.n = c->n;
             sa.rowptr = c->rowptr;
@@ -848,12 +864,14 @@ static void free_ctx(cg_ctx* c)
     if (c->graphs_std != c->graphs) destroy_graphs(c->graphs_std);
     destroy_graphs(c->graphs);
     destroy_graphs(c->graphs32);
+    destroy_graphs(c->graphs_m32);
     destroy_spmv_plan(c->spmv);
     free_multi(c);
     free_block(c);
     if (c->mixed_dev) (void)hipFree(c->mixed_dev);
     if (c->mixed_host) (void)hipHostFree(c->mixed_host);
-    void* ptrs[] = {c->rowptr, c->col, c->val, c->dinv, c->val32, c->dinv32, c->rowsum32, c->work[0], c->hist};
+    void* ptrs[] = {c->rowptr, c->col, c->val, c->dinv, c->val32, c->dinv32, c->rowsum32, c->rowsum64, c->work[0],
+                    c->hist};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -970,8 +988,9 @@ int cg_create(const cg_csr* A, const cg_opts* opts, void* hip_stream, cg_ctx** o
             JPCG_HIP(hipMemsetAsync(c->val32 + nnz, 0, sizeof(float) * kCsrPad, c->stream));
             JPCG_HIP(hipMalloc(&c->dinv32, sizeof(float) * n));
             JPCG_HIP(hipMalloc(&c->rowsum32, sizeof(float) * n));
+            JPCG_HIP(hipMalloc(&c->rowsum64, sizeof(double) * n));
             if (nnz) cast_f32_kernel<<<1024, 256, 0, c->stream>>>(nnz, c->val, c->val32);
-            rowsum_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(n, c->rowptr, c->val, c->rowsum32);
+            rowsum_kernel<<<(n + 255) / 256, 256, 0, c->stream>>>(n, c->rowptr, c->val, c->rowsum32, c->rowsum64);
             JPCG_HIP(hipGetLastError());
         }
         int* bad = nullptr;
@@ -1108,6 +1127,43 @@ int cg_solve_mixed(cg_ctx* c, const double* b, double* x, double tol, int32_t ma
         return r.status;
     } catch (const HipError& e) {
         return set_error(c, CG_EHIP, std::string("cg_solve_mixed: ") + e.what + ": " + hipGetErrorString(e.code));
+    }
+}
+
+int cg_solve_mixed_matrix(cg_ctx* c, const double* b, double* x, double tol, int32_t maxit, double drop,
+                          cg_info* info)
+{
+    if (!c) return CG_EINVAL;
+    if (!c->val32) return set_error(c, CG_EINVAL, "cg_solve_mixed_matrix: the context was created without fp32_copy");
+    if (!b || !x || b == x || !(tol >= 0.0) || !std::isfinite(tol) || !(drop >= 0.0 && drop < 1.0))
+        return set_error(c, CG_EINVAL, "cg_solve_mixed_matrix: bad arguments");
+    if (maxit <= 0) maxit = c->n;
+    if (drop == 0.0) drop = 1e-2;
+    try {
+        if (!c->graphs_m32 || c->graphs_m32->args.drop2 != drop * drop) {
+            destroy_graphs(c->graphs_m32);
+            c->graphs_m32 = nullptr;
+            c->graphs_m32 = make_graphs(c, CG_FORM_STANDARD, false, c->npl, c->bs, c->grid, c->chunk, true, drop);
+        }
+        JPCG_HIP(hipEventRecord(c->ev0, c->stream));
+        const SolveResult st = run_solve(c, c->graphs_m32, b, x, tol, maxit, nullptr);
+        JPCG_HIP(hipEventRecord(c->ev1, c->stream));
+        JPCG_HIP(hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        JPCG_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        const int status = status_of(st.stop);
+        if (info) {
+            info->iters = st.iters;
+            info->status = status;
+            info->replacements = st.replacements;
+            info->outer = 0;
+            info->relres_recur = st.nb > 0 ? std::sqrt(st.rr) / st.nb : 0.0;
+            info->relres_true = st.nb > 0 ? std::sqrt(st.rr_true) / st.nb : 0.0;
+            info->seconds = ms * 1e-3;
+        }
+        return status;
+    } catch (const HipError& e) {
+        return set_error(c, CG_EHIP, std::string("cg_solve_mixed_matrix: ") + e.what + ": " + hipGetErrorString(e.code));
     }
 }
 

@@ -38,6 +38,7 @@ struct CgState {
     double rr;       // ||r_k||^2 seen by the last continue-condition test
     double rr_true;  // ||b - A x||^2 of the returned x
     double sigma, alpha, beta;
+    double rr_ref;   // ||r||^2 after the last residual replacement (or of r0)
 };
 
 template <typename T>
@@ -53,34 +54,44 @@ struct CgArgsT {
     double* part_rep;      // [G][1]: ||b - A x||^2 for the report
     CgState* st;
     double* hist;
+    const float* val32;    // FP32-matrix form: FP32 values streamed by the direction products
+    double drop2;          // > 0: also confirm on the true residual once ||r||^2 <= drop2 rr_ref
 };
 
 // FP32 products use the row-sum-preserving evaluation (see tiles.hpp): the
 // FP32 copy of A alone would misrepresent the near-constant modes that
 // dominate x for these Neumann-plus-mass systems.
-template <typename T>
-constexpr bool kDiff = sizeof(T) == 4;
+// The FP32-matrix form (M32) streams FP32 values into an FP64 product, in
+// the same row-sum-preserving evaluation with FP64 row sums.
+template <typename T, bool M32 = false>
+constexpr bool kDiff = sizeof(T) == 4 || M32;
 
-template <int NPL, int BS, typename T>
+template <int NPL, int BS, typename T, bool M32 = false>
 struct Lds {
     double red[(BS / kWave) * 4];
-    T prod[BS * NPL * (kDiff<T> ? 2 : 1)];  // per wave: 64 * NPL products (values and entries when DIFF)
+    T prod[BS * NPL * (kDiff<T, M32> ? 2 : 1)];  // per wave: 64 * NPL products (values and entries when DIFF)
 };
 
-template <int NPL, typename T>
+template <int NPL, typename T, bool M32 = false>
 __device__ __forceinline__ T* wave_prod(T* prod)
 {
-    return prod + (threadIdx.x / kWave) * (kWave * NPL * (kDiff<T> ? 2 : 1));
+    return prod + (threadIdx.x / kWave) * (kWave * NPL * (kDiff<T, M32> ? 2 : 1));
 }
 
-// The tile walk in the evaluation that suits T.
-template <int NPL, typename T, typename Gather, typename Value, typename Pre, typename Self, typename Row,
-          typename Prologue>
-__device__ __forceinline__ void walk(const SysView<T>& s, const T* rowsum, const TileMap& tm, int L, T* prod,
-                                     Gather gather, Value value, Pre pre, Self self, Row row, Prologue prologue)
+// The tile walk in the evaluation that suits T (and the FP32-matrix form).
+template <int NPL, typename T, bool M32 = false, typename Gather, typename Value, typename Pre, typename Self,
+          typename Row, typename Prologue>
+__device__ __forceinline__ void walk(const CgArgsT<T>& a, int L, T* prod, Gather gather, Value value, Pre pre,
+                                     Self self, Row row, Prologue prologue)
 {
-    tile_rows_x<NPL, T, kDiff<T>>(s.rowptr, s.col, s.val, rowsum, tm, L, wave_prod<NPL>(prod), gather, value, pre,
-                                  self, row, prologue);
+    const SysView<T>& s = a.s;
+    if constexpr (M32) {
+        tile_rows_x<NPL, T, true, float>(s.rowptr, s.col, a.val32, a.rowsum, a.tm, L, wave_prod<NPL, T, true>(prod),
+                                         gather, value, pre, self, row, prologue);
+    } else {
+        tile_rows_x<NPL, T, kDiff<T>>(s.rowptr, s.col, s.val, a.rowsum, a.tm, L, wave_prod<NPL, T>(prod), gather,
+                                      value, pre, self, row, prologue);
+    }
 }
 
 template <typename T>
@@ -99,7 +110,7 @@ __device__ __forceinline__ void tile_residual(const CgArgsT<T>& a, T* prod, T* r
     const SysView<T>& s = a.s;
     const T* __restrict__ x = s.x;
     walk<NPL, T>(
-        s, a.rowsum, a.tm, logical_of(a.G), prod, [&](int j) { return x[j]; }, Ident<T>{},
+        a, logical_of(a.G), prod, [&](int j) { return x[j]; }, Ident<T>{},
         [&](int i) { return Tri<T>{s.b[i], s.dinv[i], kDiff<T> ? x[i] : T(0)}; }, [&](const Tri<T>& t) { return t.c; },
         [&](int i, T ax, Tri<T> bd) {
             const T bi = bd.a;
@@ -126,10 +137,10 @@ __global__ __launch_bounds__(BS) void k_setup(CgArgsT<T> a)
 }
 
 // A_1: initial tests, then p_1 = z_0 (from zp[0].z), q = A p_1, p_1 into zp[1].p.
-template <int NPL, int BS, typename T>
+template <int NPL, int BS, typename T, bool M32 = false>
 __global__ __launch_bounds__(BS) void k_first(CgArgsT<T> a, double tol, int maxit)
 {
-    __shared__ Lds<NPL, BS, T> sh;
+    __shared__ Lds<NPL, BS, T, M32> sh;
     double g[3];
     wave_grid_sum<3>(a.part_setup, a.G, g);
     const double rr = g[0], rho = g[1], nb = sqrt(g[2]), thr = tol * nb;
@@ -145,6 +156,7 @@ __global__ __launch_bounds__(BS) void k_first(CgArgsT<T> a, double tol, int maxi
         st->rho[1] = rho;
         st->rr = rr;
         st->rr_true = -1.0;
+        st->rr_ref = rr;
         if (a.hist) a.hist[0] = nb > 0.0 ? sqrt(rr) / nb : 0.0;
         st->stop = nb == 0.0 ? STOP_ZERO_RHS : (sqrt(rr) <= thr ? STOP_CONV0 : RUNNING);
         if (nb == 0.0) st->rr_true = 0.0;
@@ -159,8 +171,8 @@ __global__ __launch_bounds__(BS) void k_first(CgArgsT<T> a, double tol, int maxi
     const ZPair<T>* __restrict__ z0 = a.s.zp[0];
     ZPair<T>* __restrict__ p1 = a.s.zp[1];
     double sig = 0.0;
-    walk<NPL, T>(
-        s, a.rowsum, a.tm, L, sh.prod, [&](int j) { return z0[j].z; }, Ident<T>{}, [&](int i) { return z0[i].z; },
+    walk<NPL, T, M32>(
+        a, L, sh.prod, [&](int j) { return z0[j].z; }, Ident<T>{}, [&](int i) { return z0[i].z; },
         [&](T zi) { return zi; },
         [&](int i, T qi, T pi) {
             p1[i] = ZPair<T>{T(0), pi};  // whole pair: .z is written by B_1
@@ -175,10 +187,10 @@ __global__ __launch_bounds__(BS) void k_first(CgArgsT<T> a, double tol, int maxi
 // A_k, k >= 2, parity P = k % 2.  The scalar work (reducing the previous B's
 // partials, the tests, beta) runs as the tile walk's prologue, after the
 // first gathers are issued, so its memory latency overlaps theirs.
-template <int NPL, int BS, typename T>
+template <int NPL, int BS, typename T, bool M32 = false>
 __global__ __launch_bounds__(BS) void k_direction(CgArgsT<T> a, int P)
 {
-    __shared__ Lds<NPL, BS, T> sh;
+    __shared__ Lds<NPL, BS, T, M32> sh;
     CgState* st = a.st;
     const SysView<T>& s = a.s;
     const ZPair<T>* __restrict__ zpold = a.s.zp[P ^ 1];  // {z_{k-1}, p_{k-1}}
@@ -191,6 +203,7 @@ __global__ __launch_bounds__(BS) void k_direction(CgArgsT<T> a, int P)
     __shared__ double s_g[2];
     auto prologue = [&]() -> bool {
         const int stop = st->stop, km1 = st->k, maxit = st->maxit;
+        const double rr_ref = st->rr_ref;
         const double thr = st->thr, nb = st->nb, rho_prev = st->rho[P ^ 1];
         // Wave 0 reduces the partials for the workgroup and shares them
         // through LDS (every wave calls the prologue exactly once).
@@ -211,7 +224,10 @@ __global__ __launch_bounds__(BS) void k_direction(CgArgsT<T> a, int P)
             if (a.hist) a.hist[km1] = sqrt(rr) / nb;
         }
         // The oracle's order: continue-condition, breakdown of r'z, iteration limit.
-        if (sqrt(rr) <= thr) {
+        // With drop2 (the FP32-matrix form), the true residual is also confirmed
+        // each time the recurrence residual has fallen by sqrt(drop2) since the
+        // last replacement, and replaces r if it does not pass (reliable updates).
+        if (sqrt(rr) <= thr || rr <= a.drop2 * rr_ref) {
             if (lead) st->stop = STOP_CHECK;
             return false;
         }
@@ -232,8 +248,8 @@ __global__ __launch_bounds__(BS) void k_direction(CgArgsT<T> a, int P)
         go = true;
         return true;
     };
-    walk<NPL, T>(
-        s, a.rowsum, a.tm, L, sh.prod, [&](int j) { return zpold[j]; },
+    walk<NPL, T, M32>(
+        a, L, sh.prod, [&](int j) { return zpold[j]; },
         [&](ZPair<T> zp) { return fma_t(beta, zp.p, zp.z); }, [&](int i) { return zpold[i]; },
         [&](ZPair<T> zp) { return fma_t(beta, zp.p, zp.z); },
         [&](int i, T qi, ZPair<T> zp) {
@@ -337,6 +353,7 @@ __global__ __launch_bounds__(BS) void k_check_decide(CgArgsT<T> a, int P)
         } else {
             st->stop = RUNNING;
             st->replacements += 1;
+            st->rr_ref = g[1];
         }
     }
 }
@@ -365,7 +382,7 @@ template <int NPL, int BS, typename T>
 __global__ __launch_bounds__(BS) void k_spmv(CgArgsT<T> a, const T* __restrict__ x, T* __restrict__ y)
 {
     __shared__ Lds<NPL, BS, T> sh;
-    walk<NPL, T>(a.s, a.rowsum, a.tm, logical_of(a.G), sh.prod, [&](int j) { return x[j]; }, Ident<T>{},
+    walk<NPL, T>(a, logical_of(a.G), sh.prod, [&](int j) { return x[j]; }, Ident<T>{},
                  [&](int i) { return kDiff<T> ? x[i] : T(0); }, [&](T xi) { return xi; }, [&](int i, T v, T) { y[i] = v; },
                  NoPrologue{});
 }

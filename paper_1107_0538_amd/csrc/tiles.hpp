@@ -159,10 +159,12 @@ __device__ __forceinline__ T lds_row_sum_diff(const T* prod, const T* px, int a,
 // keeps a float product accurate on the smooth near-null modes of a
 // Neumann-plus-mass operator.  `prod` is this wave's LDS slice of 64 * NPL
 // values (twice that with DIFF).
-template <int NPL, typename T, bool DIFF = false, typename Gather, typename Value, typename Pre, typename Self,
-          typename Row, typename Prologue>
+// VT is the type of the stored values (T, or float for an FP64 product that
+// streams FP32 values); products and sums are in T.
+template <int NPL, typename T, bool DIFF = false, typename VT = T, typename Gather, typename Value, typename Pre,
+          typename Self, typename Row, typename Prologue>
 __device__ __forceinline__ void tile_rows_x(const int* __restrict__ rowptr, const int* __restrict__ col,
-                                            const T* __restrict__ val, const T* __restrict__ rowsum,
+                                            const VT* __restrict__ val, const T* __restrict__ rowsum,
                                             const TileMap& tm, int L, T* prod, Gather gather, Value value, Pre pre,
                                             Self self, Row row, Prologue prologue)
 {
@@ -197,7 +199,7 @@ __device__ __forceinline__ void tile_rows_x(const int* __restrict__ rowptr, cons
                 for (int j = 0; j < NPL; ++j) {
                     const int k = k0 + lane + kWave * j;
                     const int kk = k < k1 ? k : 0;
-                    v[j] = val[kk];
+                    v[j] = (T)val[kk];
                     c[j] = base + (int)c16[kk];
                 }
             } else {
@@ -205,7 +207,7 @@ __device__ __forceinline__ void tile_rows_x(const int* __restrict__ rowptr, cons
                 for (int j = 0; j < NPL; ++j) {
                     const int k = k0 + lane + kWave * j;
                     const int kk = k < k1 ? k : 0;
-                    v[j] = val[kk];
+                    v[j] = (T)val[kk];
                     c[j] = col[kk];
                 }
             }
@@ -259,9 +261,9 @@ __device__ __forceinline__ void tile_rows_x(const int* __restrict__ rowptr, cons
             auto colk = [&](int k) { return c16 ? r0 - kCol16Bias + (int)c16[k] : col[k]; };
             if constexpr (DIFF) {
                 const T xi = self(pvi);
-                for (int k = k0 + lane; k < k1; k += kWave) acc += val[k] * (value(gather(colk(k))) - xi);
+                for (int k = k0 + lane; k < k1; k += kWave) acc += (T)val[k] * (value(gather(colk(k))) - xi);
             } else {
-                for (int k = k0 + lane; k < k1; k += kWave) acc += val[k] * value(gather(colk(k)));
+                for (int k = k0 + lane; k < k1; k += kWave) acc += (T)val[k] * value(gather(colk(k)));
             }
 #pragma unroll
             for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);

@@ -143,6 +143,22 @@ class Solver:
         info = self.cg_solve_mixed(b, x, tol, maxit_outer, tol_inner, maxit_inner)
         return x, info
 
+    def cg_solve_mixed_matrix(self, b, x, tol=1e-10, maxit=0, drop=0.0) -> dict:
+        """FP64 iteration whose products stream FP32 values (needs fp32_copy); x holds x0 and the solution."""
+        _as_device_vec(b, self.n, "b")
+        _as_device_vec(x, self.n, "x")
+        info = capi.cg_info()
+        rc = self._lib.cg_solve_mixed_matrix(self.ctx, b.data_ptr(), x.data_ptr(), float(tol), int(maxit),
+                                             float(drop), ctypes.byref(info))
+        capi.check(rc, self.ctx)
+        return info.as_dict()
+
+    def solve_mixed_matrix(self, b, x0=None, tol=1e-10, maxit=0, drop=0.0):
+        torch = _torch()
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        info = self.cg_solve_mixed_matrix(b, x, tol, maxit, drop)
+        return x, info
+
     def spmv(self, x, y=None):
         torch = _torch()
         _as_device_vec(x, self.n, "x")

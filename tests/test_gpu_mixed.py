@@ -117,3 +117,49 @@ def test_mixed_column_index_widths_agree(cuda):
         out.append((x.cpu().numpy(), info["iters"], info["outer"]))
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
     assert oracle.relres(a, b, out[0][0]) <= tol_recomputed(a.n)
+
+
+@pytest.mark.parametrize("n", [16, 51])
+def test_mixed_matrix_form_against_its_oracle(cuda, n):
+    # The FP32-matrix form (FP64 iteration, FP32 values in the products,
+    # reliable updates on the FP64 residual) against the oracle of the same
+    # algorithm.
+    from paper_1107_0538_amd import Solver
+
+    a, b = W.problem(n, 0)
+    s = Solver(a, fp32_copy=True)
+    x, info = s.solve_mixed_matrix(_t(b, cuda))
+    xo, io = oracle.pcg_mixed_matrix(a, b)
+    xg = x.cpu().numpy()
+    assert info["status"] == io["status"] == 0
+    assert abs(info["iters"] - io["iters"]) <= 2, (info, io)
+    assert np.linalg.norm(xg - xo) <= 1e-8 * np.linalg.norm(xo)
+    assert mean_removed_relerr(xg, xo) <= 1e-8
+    assert oracle.relres(a, b, xg) <= tol_recomputed(a.n)
+    # and the FP64 solution, with the constant mode (barely determined by
+    # the residual) removed
+    x64, i64 = oracle.pcg(a, b)
+    assert mean_removed_relerr(xg, x64) <= 1e-8
+
+
+def test_mixed_matrix_form_full_size(cuda):
+    # 128^3: converged on the recomputed FP64 residual, in the FP64 oracle's
+    # iterations +-2, and within 1e-8 of the stored FP64 solution on the
+    # sampled rows with the constant mode removed.
+    import json
+    import os
+
+    from paper_1107_0538_amd import Solver
+
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "q1hex128_oracle.json")))
+    a, b = W.problem(128, 0)
+    s = Solver(a, fp32_copy=True)
+    x, info = s.solve_mixed_matrix(_t(b, cuda))
+    xg = x.cpu().numpy()
+    f = g["forms"]["standard"]
+    assert info["status"] == 0 and oracle.relres(a, b, xg) <= tol_recomputed(a.n)
+    rows = np.asarray(g["rows"])
+    dg = xg[rows] - xg.mean()
+    do = np.asarray(f["x_rows"]) - f["x_mean"]
+    assert np.linalg.norm(dg - do) <= 1e-8 * np.linalg.norm(do)
+    assert abs(info["iters"] - f["iters"]) <= 2, info

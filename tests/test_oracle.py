@@ -264,3 +264,48 @@ def test_learned_family_attainable_accuracy():
         x, info = oracle.pcg(a, b, tol=1e-10, maxit=3 * i8["iters"])
         assert info["status"] == oracle.MAXIT and info["replacements"] >= 2
         assert info["relres_true"] > 1e-10
+
+
+def test_mixed_matrix_form_tracks_fp64():
+    # The FP32-matrix form is the FP64 iteration on a perturbed operator
+    # (values rounded to single precision, row sums kept in double) with
+    # reliable updates on the FP64 residual: it must meet the tolerance on
+    # the FP64 residual in about the FP64 oracle's iterations, within 1e-8 of
+    # its solution once the constant mode is removed.
+    from conftest import mean_removed_relerr
+
+    for n, seed in ((12, 0), (16, 0), (16, 3)):
+        a, b = W.problem(n, seed)
+        x, i = oracle.pcg(a, b, tol=1e-10)
+        for drop in (1e-1, 1e-2, 1e-3):
+            xm, im = oracle.pcg_mixed_matrix(a, b, tol=1e-10, drop=drop)
+            assert im["status"] == oracle.CONVERGED and im["relres_true"] <= 1e-10
+            assert abs(im["iters"] - i["iters"]) <= 2
+            # The constant mode (A 1 is only the small mass term) is barely
+            # determined by a 1e-10 residual, so the distance to the FP64
+            # solution is judged with that mode removed.
+            assert mean_removed_relerr(xm, x) <= 1e-8
+            # one replacement per factor drop of residual reduction (10 decades to 1e-10)
+            assert im["replacements"] >= int(10 / -np.log10(drop)) - 1
+        # Without the updates the recurrence stalls above the tolerance (the
+        # FP32 values move the fixed point away from A^-1 b).
+        _, i0 = oracle.pcg_mixed_matrix(a, b, tol=1e-10, drop=0.0, maxit=4 * i["iters"])
+        assert i0["status"] == oracle.MAXIT
+
+
+def test_mixed_matrix_form_exact_values():
+    # Values already in single precision (dyadic entries): the only difference
+    # from the plain product is the row-sum-preserving evaluation, so the
+    # iterates equal the plain oracle's to rounding.
+    rng = np.random.default_rng(4)
+    n = 30
+    B = rng.integers(-4, 5, (n, n)).astype(float)
+    d = B @ B.T / 8.0 + np.eye(n) * 4.0
+    rowptr = np.arange(0, n * n + 1, n, dtype=np.int32)
+    a = W.CSR(n, rowptr, np.tile(np.arange(n, dtype=np.int32), n), d.reshape(-1))
+    assert np.array_equal(a.val.astype(np.float32).astype(np.float64), a.val)
+    b = rng.standard_normal(n)
+    for k in (1, 3, 8):
+        x, _ = oracle.pcg(a, b, maxit=k, tol=1e-14)
+        xm, _ = oracle.pcg_mixed_matrix(a, b, maxit=k, tol=1e-14, drop=0.0)
+        assert np.linalg.norm(xm - x) <= 1e-12 * np.linalg.norm(x)
