@@ -1,9 +1,10 @@
 // Device and host helpers shared by the solver kernels (gfx950, wave64).
 //
-// Everything reduces in a fixed order: a wave reduces with an xor butterfly
-// (IEEE addition is commutative, so every lane ends with the same bits), a
-// block adds its waves in index order, and a grid reduction adds per-block
-// partials in a fixed strided order followed by the same block reduction.
+// Everything reduces in a fixed order: a wave reduces by pairwise exchanges
+// (each lane adds its partner's value, and IEEE addition is commutative, so
+// both partners, and in the end every lane, hold the same bits), a block adds
+// its waves in index order, and a grid reduction adds per-block partials in a
+// fixed strided order followed by the same block reduction.
 // Repeated runs with the same launch shape are therefore bitwise identical,
 // and every block that reduces the same partials obtains the same scalar,
 // which keeps the control flow of all blocks in step.
@@ -33,6 +34,47 @@ __device__ __forceinline__ T group_sum(T v)
     return v;
 }
 
+// Sum of a double over the 64 lanes of a fully active wave, the same bits in
+// every lane.  Within each row of 16 lanes four DPP exchanges pair lane i with
+// i ^ 1, i ^ 2, 7 - i (within 8) and 15 - i: after each, the lanes of the
+// pairs merged so far hold one value, so the next exchange adds two equal
+// groups.  The four row sums are then read as scalars (lanes 0, 16, 32, 48)
+// and added as (r0 + r1) + (r2 + r3).  DPP moves run in the vector ALU, not
+// through the LDS crossbar that a lane shuffle takes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
+template <int K>
+__device__ __forceinline__ void wave_sum(double (&v)[K])
+{
+    constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowHalfMirror = 0x141, kRowMirror = 0x140;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp_move<kQuadXor1>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp_move<kQuadXor2>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp_move<kRowHalfMirror>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] += dpp_move<kRowMirror>(v[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        v[k] = (read_lane(v[k], 0) + read_lane(v[k], 16)) + (read_lane(v[k], 32) + read_lane(v[k], 48));
+}
+
 // Sum K values over the block; the totals are returned in every thread.
 // `lds` must hold (BS / 64) * K doubles.
 template <int BS, int K>
@@ -40,8 +82,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* lds)
 {
     constexpr int NW = BS / kWave;
     const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = group_sum<kWave>(v[k]);
+    wave_sum<K>(v);
     __syncthreads();
     if (l == 0) {
 #pragma unroll
@@ -84,9 +125,9 @@ __device__ __forceinline__ void grid_sum(const double* part, int G, double (&out
 }
 
 // Every WAVE reduces the G interleaved K-tuples itself: lane l adds entries
-// l, l+64, ... in order, then an xor butterfly gives every lane the same
-// bits.  No LDS and no workgroup barrier, so the loads can overlap other work
-// issued before the first use of the result.
+// l, l+64, ... in order, then pairwise lane exchanges give every lane the same
+// bits (wave_sum).  No LDS and no workgroup barrier, so the loads can overlap
+// other work issued before the first use of the result.
 template <int K>
 __device__ __forceinline__ void wave_grid_sum(const double* __restrict__ part, int G, double (&out)[K])
 {
@@ -98,8 +139,7 @@ __device__ __forceinline__ void wave_grid_sum(const double* __restrict__ part, i
 #pragma unroll
         for (int k = 0; k < K; ++k) out[k] += part[j * K + k];
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = group_sum<kWave>(out[k]);
+    wave_sum<K>(out);
 }
 
 // ---------------------------------------------------------------------------
