@@ -6,7 +6,7 @@
 // Per iteration, on N x 64 row-major FP64 blocks (columns >= s are zero):
 //   Q = A P                                  k_bc_spmm (row products, lane = column)
 //   Gamma = P'Q, Psi = P'R                   k_bc_gram<2> + k_bc_sum
-//   alpha = Gamma^-1 Psi                     k_bc_alpha (one workgroup: Cholesky over
+//   alpha = Gamma^-1 Psi                     k_bc_alpha (one wave: Cholesky over
 //                                            the live columns, inverse factor)
 //   X += P alpha                             k_bc_gemm<XUP>
 //   R -= Q alpha, Z = M^-1 R, ||r_j||^2      k_bc_gemm<RUP> + k_bc_sum
@@ -18,13 +18,15 @@
 // The Gram and block-times-64x64 products are dense contractions: they run on
 // the FP64 matrix cores (v_mfma_f64_16x16x4f64), operands straight from
 // global memory into the fragment layout.  The 64 x 64 factorisations run in
-// one workgroup.  All kernels of an iteration are captured in hipGraph chunks
-// and return at entry once the state is no longer RUN; the host confirms a
+// one wave of one workgroup, the matrix held in registers.  All kernels of an
+// iteration are captured in hipGraph chunks and return at entry once the
+// state is no longer RUN; the host confirms a
 // passed recurrence test on the true residuals and restarts the block from
 // them if a column fails.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "spmm.hpp"
 
@@ -372,71 +374,143 @@ __global__ void k_bc_pack(int n, int s, const double* __restrict__ src, double* 
 constexpr int kSmallBS = 256;
 constexpr int kSP = 65;  // LDS pitch
 
-// In-place Cholesky of the symmetric matrix A (lower triangle used) taking
-// columns in order.  mode 0: every column in `use` must have a positive pivot
-// (bad = 1 otherwise); mode 1: a column whose pivot is <= tau is dropped.
-// keep[k] is set for the factored columns; dropped or unused columns of A
-// become zero.  Thread t: lane j = t % 64 owns column j; wave g updates the
-// rows i = g (mod 4), so every LDS access of a wave is one row (conflict
-// free) or a broadcast.
-__device__ void small_cholesky(double* A, const int* use, int mode, double tau, int* keep, int* bad)
+// Cholesky factorisation of the symmetric matrix in A (its lower triangle)
+// taking columns in order.  mode 0: every column in `use` must have a
+// positive pivot (bad = 1 otherwise); mode 1: a column whose pivot is <= tau
+// is dropped.  keep[k] is set for the factored columns.  On return row k of A
+// holds column k of the factor L (A = L' in its upper triangle, zeros below
+// the diagonal; zero rows for dropped or unused columns).  Called by the whole
+// workgroup; wave 0 factors alone, without workgroup barriers: lane j holds
+// column j of the trailing matrix in registers, updated in both triangles so
+// that it stays exactly symmetric (lane i's update of a_ji is the same fused
+// product as lane j's of a_ij).  Step k: the pivot is lane k's a_kk; lane i's
+// own a_ik scaled by the inverse pivot is l_ik, written to A[k][i]; every lane
+// reads that row's entries right of the diagonal as broadcasts and subtracts
+// l_ik l_jk from its column.
+template <int K>
+__device__ __forceinline__ void chol_step(double (&a)[kB], int j, unsigned long long usem, int mode, double tau,
+                                          double* A, int* keep, bool& badk)
 {
-    const int t = threadIdx.x, j = t & 63, g = t >> 6;
-    for (int k = 0; k < kB; ++k) {
-        __syncthreads();
-        const double d = A[k * kSP + k];
-        bool kk = use[k] != 0;
-        if (kk) {
-            if (mode == 0) {
-                if (!(d > 0.0) || !isfinite(d)) {
-                    if (t == 0) *bad = 1;
-                    kk = false;
-                }
-            } else if (!(d > tau)) {
+    const double d = read_lane(a[K], K);
+    bool kk = ((usem >> K) & 1ull) != 0;
+    if (kk) {
+        if (mode == 0) {
+            if (!(d > 0.0) || !isfinite(d)) {
+                badk = true;
                 kk = false;
             }
+        } else if (!(d > tau)) {
+            kk = false;
         }
-        __syncthreads();  // every thread has read the pivot
-        if (t == 0) keep[k] = kk ? 1 : 0;
-        if (!kk) {
-            if (t < kB) A[t * kSP + k] = 0.0;
-            continue;
-        }
-        const double piv = sqrt(d), ip = 1.0 / piv;
-        if (t < kB) {
-            if (t > k) A[t * kSP + k] *= ip;
-            else if (t == k) A[k * kSP + k] = piv;
-        }
-        __syncthreads();
-        const double ljk = j > k ? A[j * kSP + k] : 0.0;
-        for (int i = k + 1 + ((g - (k + 1)) & 3); i < kB; i += 4) {
-            const double lik = A[i * kSP + k];
-            if (j > k && j <= i) A[i * kSP + j] -= lik * ljk;
-        }
+    }
+    if (j == 0) keep[K] = kk ? 1 : 0;
+    if (!kk) {
+        A[K * kSP + j] = 0.0;
+        return;
+    }
+    const double piv = sqrt(d), ip = 1.0 / piv;
+    const double l = j == K ? piv : (j > K ? a[K] * ip : 0.0);
+    A[K * kSP + j] = l;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Columns j <= K are final: they subtract l_ik * 0, which leaves a_ij
+    // unchanged (the entries are finite).  The row is read in groups of 16,
+    // all loads of a group issued before its updates.
+    const double lm = j > K ? l : 0.0;
+    constexpr int I0 = K + 1, NI = kB - I0;
+#pragma unroll
+    for (int c = 0; c < NI; c += 16) {
+        double li[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (c + u < NI) li[u] = A[K * kSP + I0 + c + u];
+        __builtin_amdgcn_sched_barrier(0);  // the group's loads stay ahead of its updates
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (c + u < NI) a[I0 + c + u] = __builtin_fma(-li[u], lm, a[I0 + c + u]);
+    }
+}
+
+template <int... K>
+__device__ __forceinline__ void chol_steps(std::integer_sequence<int, K...>, double (&a)[kB], int j,
+                                           unsigned long long usem, int mode, double tau, double* A, int* keep,
+                                           bool& badk)
+{
+    (chol_step<K>(a, j, usem, mode, tau, A, keep, badk), ...);
+}
+
+__device__ __forceinline__ void small_cholesky(double* A, const int* use, int mode, double tau, int* keep, int* bad)
+{
+    if (threadIdx.x < kB) {
+        const int j = threadIdx.x;
+        const unsigned long long usem = __ballot(use[j] != 0);
+        double a[kB];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) a[i] = A[i >= j ? i * kSP + j : j * kSP + i];
+        // Every lane has read its column before row 0 is overwritten.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        bool badk = false;
+        chol_steps(std::make_integer_sequence<int, kB>{}, a, j, usem, mode, tau, A, keep, badk);
+        if (j == 0 && badk) *bad = 1;
     }
     __syncthreads();
 }
 
-// X = Lk^-1 for the lower-triangular factor restricted to the kept columns
-// (rows and columns not kept are zero in X).  Row by row: X[i][j] =
-// (delta_ij - sum_{m<i} L[i][m] X[m][j]) / L[i][i] (X[m][j] = 0 for m < j);
-// wave g adds the terms m = g (mod 4) for lane j, and the four wave sums are
-// added in wave order.  L[i][m] is a broadcast and X[m][.] one row.
-__device__ void small_tri_inverse(const double* Lm, const int* keep, double* X, double* tmp)
+// Step M of the forward substitution (M a template parameter): x_M = r_M /
+// L[M][M], then r_i -= L[i][M] x_M for the rows below, L's column M read from
+// row M of U = L' as broadcasts.
+template <int M>
+__device__ __forceinline__ void inv_step(double (&r)[kB], unsigned long long km, const double* U)
 {
-    const int t = threadIdx.x, j = t & 63, g = t >> 6;
-    for (int e = t; e < kB * kSP; e += kSmallBS) X[e] = 0.0;
-    for (int i = 0; i < kB; ++i) {
-        __syncthreads();
-        if (!keep[i]) continue;
-        double s = 0.0;
-        for (int m = g; m < i; m += 4) s += Lm[i * kSP + m] * X[m * kSP + j];
-        tmp[g * kB + j] = s;
-        __syncthreads();
-        if (t < kB && keep[j] && j <= i) {
-            const double acc = ((tmp[j] + tmp[kB + j]) + tmp[2 * kB + j]) + tmp[3 * kB + j];
-            X[i * kSP + j] = ((j == i ? 1.0 : 0.0) - acc) / Lm[i * kSP + i];
-        }
+    if (!((km >> M) & 1ull)) {
+        r[M] = 0.0;
+        return;
+    }
+    const double xm = r[M] / U[M * kSP + M];
+    r[M] = xm;
+    // The row is read in groups of 16, all loads of a group issued before
+    // its updates.
+    constexpr int I0 = M + 1, NI = kB - I0;
+#pragma unroll
+    for (int c = 0; c < NI; c += 16) {
+        double ui[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (c + u < NI) ui[u] = U[M * kSP + I0 + c + u];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (c + u < NI) r[I0 + c + u] = __builtin_fma(-ui[u], xm, r[I0 + c + u]);
+    }
+}
+
+template <int... M>
+__device__ __forceinline__ void inv_steps(std::integer_sequence<int, M...>, double (&r)[kB], unsigned long long km,
+                                          const double* U)
+{
+    (inv_step<M>(r, km, U), ...);
+}
+
+// X = Lk^-1 for the factor left in U = L' by small_cholesky, restricted to the
+// kept columns (rows and columns not kept are zero in X).  Wave 0 alone: lane j
+// forms column j by forward substitution in column order (each x_m, once
+// known, updates every row below it, so the updates of a step are
+// independent).
+__device__ __forceinline__ void small_tri_inverse(const double* U, const int* keep, double* X)
+{
+    if (threadIdx.x < kB) {
+        const int j = threadIdx.x;
+        const unsigned long long km = __ballot(keep[j] != 0);
+        const bool mine = ((km >> j) & 1ull) != 0;
+        double r[kB];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) r[i] = i == j ? 1.0 : 0.0;
+        inv_steps(std::make_integer_sequence<int, kB>{}, r, km, U);
+#pragma unroll
+        for (int i = 0; i < kB; ++i) X[i * kSP + j] = mine ? r[i] : 0.0;
     }
     __syncthreads();
 }
@@ -509,7 +583,7 @@ __device__ void load_small(const double* src, double* dst)
 __global__ __launch_bounds__(kSmallBS) void k_bc_alpha(BcState* st, int gate)
 {
     if (bc_stopped(st, gate)) return;
-    __shared__ double A[kB * kSP], X[kB * kSP], T[kB * kSP], tmp[4 * kB];
+    __shared__ double A[kB * kSP], X[kB * kSP], T[kB * kSP];
     __shared__ int use[kB], keep[kB], bad;
     if (threadIdx.x == 0) bad = 0;
     if (threadIdx.x < kB) use[threadIdx.x] = st->live[threadIdx.x];
@@ -519,7 +593,7 @@ __global__ __launch_bounds__(kSmallBS) void k_bc_alpha(BcState* st, int gate)
         if (threadIdx.x == 0) st->status = BC_BREAKDOWN;
         return;
     }
-    small_tri_inverse(A, keep, X, tmp);
+    small_tri_inverse(A, keep, X);
     for (int e = threadIdx.x; e < kBB; e += kSmallBS) st->Li[e] = X[(e / kB) * kSP + e % kB];
     load_small(st->G1, A);
     small_matmul_lds(X, 0, A, T);                             // T = Li Psi
@@ -535,18 +609,19 @@ __global__ __launch_bounds__(kSmallBS) void k_bc_beta(BcState* st, int gate)
     __shared__ double A[kB * kSP], X[kB * kSP], T[kB * kSP];
     __shared__ int decide;
     const int t = threadIdx.x;
-    if (t == 0) {
-        bool pass = true, finite = true;
-        for (int j = 0; j < kB; ++j) {
-            pass = pass && st->rr[j] <= st->thr2[j];
-            finite = finite && isfinite(st->rr[j]);
-        }
+    if (t < kB) {
+        // Lane j tests column j; the ballots give every lane the verdicts.
+        const double rj = st->rr[t];
+        const bool pass = __ballot(rj <= st->thr2[t]) == ~0ull;
+        const bool finite = __ballot(isfinite(rj)) == ~0ull;
         int s = BC_RUN;
         if (!finite) s = BC_BREAKDOWN;
         else if (pass) s = BC_PENDING;
         else if (st->k >= st->maxit) s = BC_MAXIT;
-        st->status = s;
-        decide = s;
+        if (t == 0) {
+            st->status = s;
+            decide = s;
+        }
     }
     __syncthreads();
     if (decide != BC_RUN) return;
@@ -565,7 +640,7 @@ __global__ __launch_bounds__(kSmallBS) void k_bc_beta(BcState* st, int gate)
 __global__ __launch_bounds__(kSmallBS) void k_bc_orth(BcState* st, int pass, int gate)
 {
     if (bc_stopped(st, gate)) return;
-    __shared__ double A[kB * kSP], X[kB * kSP], tmp[4 * kB], scale[kB];
+    __shared__ double A[kB * kSP], X[kB * kSP], scale[kB];
     __shared__ int use[kB], keep[kB], bad;
     __shared__ double shift;
     const int t = threadIdx.x;
@@ -594,7 +669,7 @@ __global__ __launch_bounds__(kSmallBS) void k_bc_orth(BcState* st, int pass, int
         __syncthreads();
     }
     small_cholesky(A, use, 1, pass == 0 ? 0.0 : st->tau, keep, &bad);
-    small_tri_inverse(A, keep, X, tmp);
+    small_tri_inverse(A, keep, X);
     // M[i][j] = scale_i X[j][i]
     for (int e = t; e < kBB; e += kSmallBS) {
         const int i = e / kB, j = e % kB;
