@@ -58,7 +58,15 @@ def solve_bytes(n, nnz, iters, checks, form="standard", vb=8, ib=4):
 # records the profile it came from and a hash of the kernel sources it was
 # measured on; once those sources change the figure no longer applies and the
 # roofline reports traffic as null.
-MEASURED_TRAFFIC = {}
+# HBM bytes per iteration from rocprofv3 FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch,
+# median; FETCH_SIZE x2 and WRITE_SIZE x1, the factors a streaming triad of known size reads
+# under the same counters), valid while the kernels' sources hash to `sources_sha`.
+MEASURED_TRAFFIC = {
+    ("standard", 132651, 3442951, 16, 512, 16): {  # k_direction + k_update
+        "bytes": ((18563.4 + 3146.4) * 2 + 3159.2 + 4149.4) * 1024, "sources_sha": "dde6e28c68226766"},
+    ("single", 132651, 3442951, 16, 512, 16): {  # k_sr_iter
+        "bytes": (21074.1 * 2 + 6298.4) * 1024, "sources_sha": "ecffa30fce08bee6"},
+}
 TRAFFIC_SOURCES = {
     "standard": ("std_kernels.hpp", "tiles.hpp", "common.hpp"),
     "single": ("sr_kernels.hpp", "tiles.hpp", "common.hpp"),
