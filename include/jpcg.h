@@ -191,7 +191,9 @@ int cg_solve_mixed(cg_ctx *ctx, const double *b, double *x, double tol, int32_t 
  * 1e-2; 0 < drop < 1), and at the continue-condition, the FP64 true residual
  * either confirms convergence or replaces r, and the iteration continues.
  * Requires fp32_copy.  Same arguments, statuses and info as cg_solve
- * (replacements counts every replaced residual).
+ * (replacements counts every replaced residual).  Every replacement drains
+ * the graph chunk in flight, so unless opts.chunk was set this form launches
+ * chunks of at most 8 iterations.
  */
 int cg_solve_mixed_matrix(cg_ctx *ctx, const double *b, double *x, double tol, int32_t maxit, double drop,
                           cg_info *info);
